@@ -1,0 +1,216 @@
+"""FP64 CPU oracle for the Tau1 lattice Boltzmann update (test infrastructure).
+
+Only the test suite, the smoke check and the CPU-baseline leg of the benchmark
+may import this package.  It wraps ``tau1_oracle.c`` (plain C, FP64, built with
+``-O2 -ffp-contract=off``) through ctypes and shares nothing with the GPU path.
+
+Functions follow the paper's statement of the method:
+
+* :func:`run` -- Eq. (8)-(10) in drho form with halfway bounce-back (Eq. (11)),
+  periodic wrap and velocity-shift body forcing; the parity target.
+* :func:`bgk_run` -- brute-force standard LBGK, Eq. (4), full populations; at
+  omega = 1 it must equal :func:`run` exactly.
+* :func:`run_rhoform` -- the same update with rho stored and Eq. (3) evaluated
+  as printed.
+* :func:`step_nodes` -- one update at chosen nodes from a full state.
+* :func:`reduce` -- mass and Darcy permeability.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "tau1_oracle.c")
+_LIB = os.path.join(_HERE, "libtau1_oracle.so")
+
+CFLAGS = ["-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
+          "-std=c99", "-Wall", "-Wextra", "-shared", "-fPIC"]
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc; returns the library path."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        subprocess.run(["gcc", *CFLAGS, _SRC, "-o", tmp, "-lm"], check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class _Lib:
+    """ctypes handle on one build of the oracle library."""
+
+    def __init__(self, path: str):
+        lib = ctypes.CDLL(path)
+        P = ctypes.c_void_p
+        L = ctypes.c_long
+        I = ctypes.c_int
+        D = ctypes.c_double
+        lib.tau1o_lattice.argtypes = [I, P, P, P]
+        lib.tau1o_run.argtypes = [I, L, L, L, P, P, P, P, P, P, L, I]
+        lib.tau1o_run_rhoform.argtypes = [I, L, L, L, P, P, P, P, P, P, L, I]
+        lib.tau1o_bgk_run.argtypes = [I, L, L, L, P, P, P, P, P, P, D, L, I]
+        lib.tau1o_step_nodes.argtypes = [I, L, L, L, P, P, P, P, P, P, L, P, P, I]
+        lib.tau1o_reduce.argtypes = [L, L, L, P, P, P, P, P, I, D, P, P]
+        lib.tau1o_threads.restype = I
+        self.lib = lib
+
+
+_default = None
+_override = None
+
+
+def _load():
+    global _default
+    if _override is not None:
+        return _override.lib
+    if _default is None:
+        if not os.path.exists(_LIB):
+            build(force=True)
+        _default = _Lib(_LIB)
+    return _default.lib
+
+
+class use_library:
+    """Context manager: route this module's calls to another oracle build
+    (used by the mutation tests, which compile deliberately broken copies)."""
+
+    def __init__(self, path: str):
+        self._lib = _Lib(path)
+
+    def __enter__(self):
+        global _override
+        self._prev = _override
+        _override = self._lib
+        return self
+
+    def __exit__(self, *exc):
+        global _override
+        _override = self._prev
+        return False
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def threads() -> int:
+    """OpenMP threads the oracle uses by default."""
+    return int(_load().tau1o_threads())
+
+
+def lattice(q: int):
+    """Direction vectors c (q x 3 int), weights w (q) and opposite map (q)."""
+    c = np.zeros((q, 3), dtype=np.int32)
+    w = np.zeros(q, dtype=np.float64)
+    opp = np.zeros(q, dtype=np.int32)
+    if _load().tau1o_lattice(q, _ptr(c), _ptr(w), _ptr(opp)) != q:
+        raise ValueError(f"unsupported lattice q={q}")
+    return c, w, opp
+
+
+class State:
+    """drho = rho - 1 and velocity (ux, uy, uz), FP64, index x + nx*(y + ny*z).
+
+    Arrays are 3-D with shape (nz, ny, nx) so that x is the fastest axis.
+    """
+
+    def __init__(self, solid: np.ndarray, drho=None, u=None):
+        solid = np.ascontiguousarray(solid, dtype=np.uint8)
+        if solid.ndim != 3:
+            raise ValueError("solid must be (nz, ny, nx)")
+        self.solid = solid
+        shape = solid.shape
+        self.drho = (np.zeros(shape) if drho is None
+                     else np.array(drho, dtype=np.float64, copy=True).reshape(shape))
+        if u is None:
+            self.u = np.zeros((3,) + shape)
+        else:
+            self.u = np.array(u, dtype=np.float64, copy=True).reshape((3,) + shape)
+        self.drho = np.ascontiguousarray(self.drho)
+        self.u = np.ascontiguousarray(self.u)
+
+    @property
+    def dims(self):
+        nz, ny, nx = self.solid.shape
+        return nx, ny, nz
+
+    def copy(self) -> "State":
+        return State(self.solid, self.drho, self.u)
+
+
+def _g(g):
+    return np.ascontiguousarray(np.asarray(g, dtype=np.float64).reshape(3))
+
+
+def run(q: int, st: State, g, nsteps: int, nthreads: int = 0) -> State:
+    """Advance a copy of ``st`` by ``nsteps`` Tau1 updates (drho form)."""
+    out = st.copy()
+    nx, ny, nz = out.dims
+    gg = _g(g)
+    rc = _load().tau1o_run(q, nx, ny, nz, _ptr(out.solid), _ptr(out.drho),
+                           _ptr(out.u[0]), _ptr(out.u[1]), _ptr(out.u[2]),
+                           _ptr(gg), nsteps, nthreads)
+    if rc != 0:
+        raise RuntimeError(f"tau1o_run failed ({rc})")
+    return out
+
+
+def run_rhoform(q: int, st: State, g, nsteps: int, nthreads: int = 0) -> State:
+    """Same as :func:`run` but evaluated with rho stored (Eq. (3) as printed)."""
+    out = st.copy()
+    rho = np.ascontiguousarray(1.0 + out.drho)
+    nx, ny, nz = out.dims
+    gg = _g(g)
+    rc = _load().tau1o_run_rhoform(q, nx, ny, nz, _ptr(out.solid), _ptr(rho),
+                                   _ptr(out.u[0]), _ptr(out.u[1]), _ptr(out.u[2]),
+                                   _ptr(gg), nsteps, nthreads)
+    if rc != 0:
+        raise RuntimeError(f"tau1o_run_rhoform failed ({rc})")
+    out.drho = rho - 1.0
+    return out
+
+
+def bgk_run(q: int, st: State, g, nsteps: int, omega: float = 1.0,
+            nthreads: int = 0) -> State:
+    """Brute-force standard LBGK with populations; returns its moments."""
+    out = st.copy()
+    nx, ny, nz = out.dims
+    gg = _g(g)
+    rc = _load().tau1o_bgk_run(q, nx, ny, nz, _ptr(out.solid), _ptr(out.drho),
+                               _ptr(out.u[0]), _ptr(out.u[1]), _ptr(out.u[2]),
+                               _ptr(gg), float(omega), nsteps, nthreads)
+    if rc != 0:
+        raise RuntimeError(f"tau1o_bgk_run failed ({rc})")
+    return out
+
+
+def step_nodes(q: int, st: State, g, idx, nthreads: int = 0) -> np.ndarray:
+    """One update at flat node indices ``idx``; returns (len(idx), 4)."""
+    idx = np.ascontiguousarray(np.asarray(idx, dtype=np.int64).ravel())
+    out = np.zeros((idx.size, 4), dtype=np.float64)
+    nx, ny, nz = st.dims
+    gg = _g(g)
+    rc = _load().tau1o_step_nodes(q, nx, ny, nz, _ptr(st.solid), _ptr(st.drho),
+                                  _ptr(st.u[0]), _ptr(st.u[1]), _ptr(st.u[2]),
+                                  _ptr(gg), idx.size, _ptr(idx), _ptr(out),
+                                  nthreads)
+    if rc != 0:
+        raise RuntimeError(f"tau1o_step_nodes failed ({rc})")
+    return out
+
+
+def reduce(st: State, axis: int, g_axis: float):
+    """(mass, permeability) of a state; see tau1o_reduce."""
+    m = np.zeros(1)
+    k = np.zeros(1)
+    nx, ny, nz = st.dims
+    rc = _load().tau1o_reduce(nx, ny, nz, _ptr(st.solid), _ptr(st.drho),
+                              _ptr(st.u[0]), _ptr(st.u[1]), _ptr(st.u[2]),
+                              axis, float(g_axis), _ptr(m), _ptr(k))
+    if rc != 0:
+        raise RuntimeError("tau1o_reduce failed")
+    return float(m[0]), float(k[0])
