@@ -1,0 +1,165 @@
+/*
+ * tau1.h -- C ABI of the MI355X (gfx950) Tau1 lattice Boltzmann library.
+ *
+ * Method (Bacza, Tomczak, Matyka, "The lattice Boltzmann method for fluid
+ * flows at relaxation time equal one: performance study"): with relaxation
+ * time tau = 1 the LBGK update of Eq. (4) reduces to Eq. (8), so only the
+ * density and velocity are stored (two copies, "AB" layout).  Each fluid node
+ * gathers rho and u of its neighbours x - c_k, forms the equilibrium of
+ * Eq. (3) for direction k and sums them into the new rho and momentum
+ * (Eqs. (9)-(10)); the velocity is the momentum times one reciprocal of rho
+ * (the division-saving algorithm of the implementation section).  Links to
+ * solid nodes use halfway bounce-back with the population rebuilt from the
+ * node's own previous rho*, u* (Eq. (11)).  All axes are periodic; walls are
+ * solid nodes.  A body force g (an acceleration, lattice units) enters as a
+ * velocity shift: the equilibrium is evaluated at u + g/2 and the reported
+ * velocity is j/rho + g/2.
+ *
+ * Lattices D3Q15, D3Q19, D3Q27 (the 3-D sets of the complexity table).
+ * Node index: x + nx*(y + ny*z), x fastest.  Every size is in nodes unless
+ * stated.
+ *
+ * Memory: the library never allocates device memory.  The caller queries
+ * tau1_workspace_size and passes a device buffer of at least that many bytes
+ * (for example a torch uint8 tensor); the buffer and the HIP stream are
+ * borrowed and must outlive the context.  The context owns only host-side
+ * metadata and its HIP graphs.  Host arrays passed in are copied during the
+ * call; host output arrays are written during the call.
+ *
+ * Errors: every call returns a tau1_status; no C++ exception crosses the ABI.
+ * On error, output arguments are left untouched and a failed create leaves
+ * *out == NULL.  TAU1_E_HIP is sticky: the context must be destroyed.
+ * tau1_step only enqueues work; device faults surface at the next call that
+ * synchronises (tau1_moments, tau1_permeability, tau1_sync).
+ *
+ * Threading: a context is not thread-safe; distinct contexts are independent.
+ */
+#ifndef TAU1_H
+#define TAU1_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    TAU1_OK = 0,
+    TAU1_E_INVALID = -1,     /* bad argument (dims, lattice, precision, ...) */
+    TAU1_E_NOMEM = -2,       /* host allocation failed                       */
+    TAU1_E_HIP = -3,         /* a HIP runtime call or kernel failed (sticky)  */
+    TAU1_E_UNSUPPORTED = -4, /* valid request this build does not provide     */
+    TAU1_E_NONFINITE = -5,   /* a reduction or readback met NaN or Inf        */
+    TAU1_E_WORKSPACE = -6    /* workspace missing, too small or misaligned    */
+} tau1_status;
+
+typedef struct tau1_ctx tau1_ctx; /* opaque, owned by the library */
+
+typedef enum { TAU1_D3Q15 = 15, TAU1_D3Q19 = 19, TAU1_D3Q27 = 27 } tau1_lattice;
+
+/* Arithmetic and storage of (rho - 1, u):
+ *   TAU1_F64       FP64 compute, FP64 storage (parity mode);
+ *   TAU1_F32       FP32 compute, FP32 storage;
+ *   TAU1_F32_F16   FP32 compute, IEEE half storage with power-of-two scales;
+ *   TAU1_F32_BF16  FP32 compute, bfloat16 storage (round to nearest even).
+ * Mass and permeability are always reduced in FP64. */
+typedef enum {
+    TAU1_F64 = 0,
+    TAU1_F32 = 1,
+    TAU1_F32_F16 = 2,
+    TAU1_F32_BF16 = 3
+} tau1_precision;
+
+/* One lattice (one porous sample). */
+typedef struct {
+    int64_t nx, ny, nz;    /* >= 1 each; every axis periodic                  */
+    const uint8_t *solid;  /* host, N bytes; nonzero = solid node              */
+    const double *drho0;   /* host, N values of rho - 1, or NULL for rho = 1   */
+    const double *u0;      /* host, 3N values, SoA (ux | uy | uz), or NULL     */
+} tau1_sample;
+
+typedef struct {
+    int32_t lattice;        /* tau1_lattice                                    */
+    int32_t precision;      /* tau1_precision                                  */
+    int32_t n_samples;      /* >= 1; > 1 = batched, one launch per step for all */
+    int32_t graph_chunk;    /* steps per captured HIP graph; even; 0 = 100      */
+    const tau1_sample *samples;
+    double g[3];            /* body acceleration, same for every sample         */
+    void *hip_stream;       /* borrowed hipStream_t; NULL = default stream      */
+    void *workspace;        /* borrowed device memory, 256-byte aligned         */
+    size_t workspace_bytes;
+    int32_t kernel;         /* step kernel: -1 = automatic (tuned or default),
+                               0 = per-node gather, 1 = z-march tiles          */
+    int32_t tile;           /* z-march tile shape index, -1 = automatic        */
+    int32_t f16_log2_scale_rho; /* F16 storage: stored = value * 2^s; 0 = 20   */
+    int32_t f16_log2_scale_u;   /* F16 storage scale of the velocity; 0 = 20   */
+    const char *tune_cache; /* path of the autotune JSON cache, or NULL         */
+} tau1_desc;
+
+/* Static facts about a created context (host copy). */
+typedef struct {
+    int32_t lattice, precision, n_samples;
+    int32_t kernel;          /* step kernel in use                          */
+    int32_t tile;            /* tile shape index in use (z-march)           */
+    int32_t graph_chunk;
+    int64_t n_nodes;         /* all samples                                 */
+    int64_t n_fluid;         /* all samples                                 */
+    int64_t steps_done;
+    double bytes_per_step;   /* algorithmic HBM bytes of one step (all samples):
+                                2 (d+1) s per fluid node plus one mask bit per
+                                node (complexity table of the paper)        */
+} tau1_info;
+
+/* Bytes of device workspace the descriptor needs.  Host only, no GPU call. */
+tau1_status tau1_workspace_size(const tau1_desc *desc, size_t *bytes);
+
+/* Validates the descriptor, encodes the geometry (bit mask, tile classes) and
+ * uploads the initial state into the workspace.  Synchronous on the stream. */
+tau1_status tau1_create(const tau1_desc *desc, tau1_ctx **out);
+
+/* Enqueues nsteps >= 0 time steps on the stream (graph replays of graph_chunk
+ * steps plus single launches); does not wait. */
+tau1_status tau1_step(tau1_ctx *ctx, int64_t nsteps);
+
+/* Waits for the stream and reports any pending device error. */
+tau1_status tau1_sync(tau1_ctx *ctx);
+
+/* Copies the current state of one sample to host FP64 arrays: drho (N values
+ * of rho - 1) and u (3N values, SoA).  Solid nodes read rho = 1, u = 0.
+ * Either pointer may be NULL.  Synchronous.  TAU1_E_NONFINITE if any fluid
+ * value is NaN or Inf (the arrays are still written). */
+tau1_status tau1_moments(tau1_ctx *ctx, int32_t sample, double *drho,
+                         double *u);
+
+/* FP64 reductions over one sample, in a fixed order (deterministic):
+ *   mass = sum over fluid nodes of rho;
+ *   k    = nu <u_axis> / g_axis, nu = 1/6, <.> the mean over all N nodes
+ *          (Darcy permeability in lattice units; solid nodes count as 0).
+ * k may be NULL; if it is not, g[axis] must be nonzero.  Synchronous. */
+tau1_status tau1_permeability(tau1_ctx *ctx, int32_t sample,
+                              int32_t axis, double *k, double *mass);
+
+/* Times each eligible step-kernel shape for trial_steps steps (state is not
+ * advanced: trials write only the spare buffer), keeps the fastest and, if
+ * the descriptor named a cache file, records it there.  Synchronous. */
+tau1_status tau1_autotune(tau1_ctx *ctx, int32_t trial_steps);
+
+tau1_status tau1_get_info(const tau1_ctx *ctx, tau1_info *info);
+
+/* Releases host resources (graphs, metadata); NULL-safe. */
+void tau1_destroy(tau1_ctx *ctx);
+
+const char *tau1_strerror(tau1_status status);
+
+/* Copy-bandwidth probe (calibrates the achievable HBM rate, the GPU analogue
+ * of the paper's copy loop): copies bytes/2 from the first half of buf to the
+ * second half, reps times, on the stream; returns the mean seconds per copy
+ * measured with HIP events.  buf is device memory of at least `bytes`. */
+tau1_status tau1_copy_probe(void *hip_stream, void *buf, size_t bytes,
+                            int32_t reps, double *seconds);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TAU1_H */

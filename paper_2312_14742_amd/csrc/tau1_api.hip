@@ -1,0 +1,669 @@
+// tau1_api.hip -- host side of the C ABI declared in include/tau1.h:
+// descriptor validation, workspace planning, geometry encode and state
+// upload, step launches and HIP graphs, readback and FP64 reductions,
+// autotuning of the z-march tile shape.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/tau1.h"
+#include "tau1_device.hpp"
+#include "tau1_kernels.hpp"
+#include "tau1_zmarch.hpp"
+
+using namespace tau1;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+constexpr int64_t kStageNodes = int64_t(1) << 21;   // upload/readback chunk
+constexpr int kMaxSamples = 1 << 16;
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+struct SampleHost {
+    SampleDev dev;
+    int64_t n_fluid;
+};
+
+// Byte layout of the workspace for one descriptor.
+struct Plan {
+    size_t samples_off = 0;   // SampleDev[nsamples]
+    size_t partial_off = 0;   // reduction partials + result + counters
+    size_t tiles_off = 0;     // z-march work list
+    size_t stage_off = 0;     // upload / readback staging
+    size_t stage_bytes = 0;
+    size_t total = 0;
+    int64_t ntiles = 0;
+    int64_t total_blocks = 0;
+    std::vector<SampleHost> s;
+};
+
+bool valid_lattice(int q) { return q == 15 || q == 19 || q == 27; }
+bool valid_precision(int p) { return p >= kF64 && p <= kBF16; }
+
+tau1_status validate(const tau1_desc* d) {
+    if (!d) return TAU1_E_INVALID;
+    if (!valid_lattice(d->lattice) || !valid_precision(d->precision)) return TAU1_E_INVALID;
+    if (d->n_samples < 1 || d->n_samples > kMaxSamples || !d->samples) return TAU1_E_INVALID;
+    if (d->graph_chunk < 0 || (d->graph_chunk % 2) != 0) return TAU1_E_INVALID;
+    if (d->kernel < -1 || d->kernel > 1) return TAU1_E_INVALID;
+    if (d->tile < -1 || d->tile >= kNumTiles) return TAU1_E_INVALID;
+    for (int a = 0; a < 3; ++a)
+        if (!std::isfinite(d->g[a])) return TAU1_E_INVALID;
+    if (d->f16_log2_scale_rho < 0 || d->f16_log2_scale_rho > 40 ||
+        d->f16_log2_scale_u < 0 || d->f16_log2_scale_u > 40)
+        return TAU1_E_INVALID;
+    for (int i = 0; i < d->n_samples; ++i) {
+        const tau1_sample& s = d->samples[i];
+        if (s.nx < 1 || s.ny < 1 || s.nz < 1 || !s.solid) return TAU1_E_INVALID;
+        if (s.nx > (1 << 20) || s.ny > (1 << 20) || s.nz > (1 << 20)) return TAU1_E_INVALID;
+        if (s.nx * s.ny > (int64_t(1) << 31)) return TAU1_E_INVALID;
+        if (s.nx * s.ny * s.nz > (int64_t(1) << 36)) return TAU1_E_INVALID;
+    }
+    return TAU1_OK;
+}
+
+Plan make_plan(const tau1_desc* d) {
+    Plan p;
+    const int sz = storage_bytes(d->precision);
+    size_t off = 0;
+    p.samples_off = off;
+    off = align_up(off + sizeof(SampleDev) * d->n_samples, kAlign);
+    p.partial_off = off;
+    off = align_up(off + sizeof(double) * (kReduceBlocks * 4 + 8) + 64, kAlign);
+    int64_t blocks = 0, tiles = 0, maxn = 0;
+    p.s.resize(d->n_samples);
+    for (int i = 0; i < d->n_samples; ++i) {
+        const tau1_sample& in = d->samples[i];
+        SampleDev& sd = p.s[i].dev;
+        std::memset(&sd, 0, sizeof sd);
+        sd.nx = (int32_t)in.nx;
+        sd.ny = (int32_t)in.ny;
+        sd.nz = (int32_t)in.nz;
+        sd.n = in.nx * in.ny * in.nz;
+        sd.words = (int32_t)((in.nx + 31) / 32);
+        sd.stride = (int64_t)(align_up((size_t)sd.n * sz, kAlign) / sz);
+        sd.block0 = blocks;
+        blocks += (sd.n + kGatherBlock - 1) / kGatherBlock;
+        zmarch_tiling(sd);
+        sd.tile0 = tiles;
+        tiles += (int64_t)sd.tiles_y * sd.tiles_z;
+        maxn = std::max<int64_t>(maxn, sd.n);
+    }
+    p.total_blocks = blocks;
+    p.ntiles = tiles;
+    p.tiles_off = off;
+    off = align_up(off + sizeof(int32_t) * 4 * (size_t)std::max<int64_t>(tiles, 1), kAlign);
+    for (int i = 0; i < d->n_samples; ++i) {
+        SampleDev& sd = p.s[i].dev;
+        sd.mask = (int64_t)off;
+        off = align_up(off + sizeof(uint32_t) * (size_t)sd.words * sd.ny * sd.nz, kAlign);
+        for (int b = 0; b < 2; ++b) {
+            sd.state[b] = (int64_t)off;
+            off = align_up(off + (size_t)4 * sd.stride * sz, kAlign);
+        }
+    }
+    const int64_t stage_nodes = std::min<int64_t>(maxn, kStageNodes);
+    p.stage_off = off;
+    // solid byte + drho + 3 u (FP64) on upload; 4 FP64 on readback
+    p.stage_bytes = align_up((size_t)stage_nodes * 40 + kAlign, kAlign);
+    off += p.stage_bytes;
+    p.total = off;
+    return p;
+}
+
+#define HIP_TRY(expr)                                  \
+    do {                                               \
+        hipError_t _e = (expr);                        \
+        if (_e != hipSuccess) return fail_hip(ctx, _e); \
+    } while (0)
+
+}  // namespace
+
+struct tau1_ctx {
+    int lattice = 19, precision = kF32, nsamples = 1;
+    int graph_chunk = 100;
+    int kernel = 0, tile = 0;
+    hipStream_t stream = nullptr;
+    uint8_t* base = nullptr;
+    size_t ws_bytes = 0;
+    Plan plan;
+    StepArgs args[2];
+    int parity = 0;
+    int64_t steps_done = 0;
+    int64_t n_nodes = 0, n_fluid = 0;
+    tau1_status sticky = TAU1_OK;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int graph_kernel = -1, graph_tile = -1, graph_parity = -1;
+    double g[3] = {0, 0, 0};
+    std::string cache;
+    hipError_t last_hip = hipSuccess;
+};
+
+namespace {
+
+tau1_status fail_hip(tau1_ctx* ctx, hipError_t e) {
+    if (ctx) {
+        ctx->sticky = TAU1_E_HIP;
+        ctx->last_hip = e;
+    }
+    (void)hipGetLastError();
+    return TAU1_E_HIP;
+}
+
+// --- kernel dispatch -------------------------------------------------------
+template <int Q, int P>
+void* gather_fn() { return reinterpret_cast<void*>(&k_gather<Q, P>); }
+
+void* pick_gather(int q, int p) {
+    switch (q * 10 + p) {
+        case 150: return gather_fn<15, kF64>();
+        case 151: return gather_fn<15, kF32>();
+        case 152: return gather_fn<15, kF16>();
+        case 153: return gather_fn<15, kBF16>();
+        case 190: return gather_fn<19, kF64>();
+        case 191: return gather_fn<19, kF32>();
+        case 192: return gather_fn<19, kF16>();
+        case 193: return gather_fn<19, kBF16>();
+        case 270: return gather_fn<27, kF64>();
+        case 271: return gather_fn<27, kF32>();
+        case 272: return gather_fn<27, kF16>();
+        case 273: return gather_fn<27, kBF16>();
+    }
+    return nullptr;
+}
+
+// Launch geometry of one step for the chosen kernel.
+struct Launch {
+    void* fn;
+    dim3 grid, block;
+    size_t shmem;
+};
+
+bool zmarch_eligible(const tau1_ctx* ctx) {
+    return zmarch_supported(ctx->lattice, ctx->precision, ctx->plan.s.data(),
+                            (int)ctx->plan.s.size());
+}
+
+Launch step_launch(const tau1_ctx* ctx, int kernel, int tile) {
+    Launch l{};
+    if (kernel == 1) {
+        l.fn = pick_zmarch(ctx->lattice, ctx->precision, tile);
+        l.block = dim3(zmarch_threads(tile));
+        l.grid = dim3((unsigned)zmarch_grid(ctx->plan.ntiles, tile));
+        l.shmem = 0;
+    } else {
+        l.fn = pick_gather(ctx->lattice, ctx->precision);
+        l.block = dim3(kGatherBlock);
+        l.grid = dim3((unsigned)ctx->plan.total_blocks);
+        l.shmem = 0;
+    }
+    return l;
+}
+
+tau1_status launch_one(tau1_ctx* ctx, int kernel, int tile, const StepArgs& a) {
+    const Launch l = step_launch(ctx, kernel, tile);
+    if (!l.fn) return TAU1_E_UNSUPPORTED;
+    if (l.grid.x == 0) return TAU1_OK;
+    void* params[] = {const_cast<StepArgs*>(&a)};
+    HIP_TRY(hipLaunchKernel(l.fn, l.grid, l.block, params, l.shmem, ctx->stream));
+    return TAU1_OK;
+}
+
+void destroy_graph(tau1_ctx* ctx) {
+    if (ctx->exec) (void)hipGraphExecDestroy(ctx->exec);
+    if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
+    ctx->exec = nullptr;
+    ctx->graph = nullptr;
+    ctx->graph_kernel = ctx->graph_tile = -1;
+}
+
+// Graph of graph_chunk single-step kernel nodes in a chain; the parity
+// alternates node by node and, graph_chunk being even, the graph maps the
+// current buffer onto itself.  Built without stream capture.
+tau1_status build_graph(tau1_ctx* ctx) {
+    destroy_graph(ctx);
+    const Launch l = step_launch(ctx, ctx->kernel, ctx->tile);
+    if (!l.fn) return TAU1_E_UNSUPPORTED;
+    HIP_TRY(hipGraphCreate(&ctx->graph, 0));
+    hipGraphNode_t prev = nullptr;
+    for (int s = 0; s < ctx->graph_chunk; ++s) {
+        StepArgs* a = &ctx->args[(ctx->parity + s) & 1];
+        void* params[] = {a};
+        hipKernelNodeParams kp{};
+        kp.func = l.fn;
+        kp.gridDim = l.grid;
+        kp.blockDim = l.block;
+        kp.sharedMemBytes = (unsigned)l.shmem;
+        kp.kernelParams = params;
+        kp.extra = nullptr;
+        hipGraphNode_t node;
+        HIP_TRY(hipGraphAddKernelNode(&node, ctx->graph, prev ? &prev : nullptr, prev ? 1 : 0, &kp));
+        prev = node;
+    }
+    HIP_TRY(hipGraphInstantiate(&ctx->exec, ctx->graph, nullptr, nullptr, 0));
+    ctx->graph_kernel = ctx->kernel;
+    ctx->graph_tile = ctx->tile;
+    ctx->graph_parity = ctx->parity;
+    return TAU1_OK;
+}
+
+template <int P>
+tau1_status upload_sample_t(tau1_ctx* ctx, int s, const tau1_sample& in) {
+    const SampleDev& sd = ctx->plan.s[s].dev;
+    uint8_t* stage = ctx->base + ctx->plan.stage_off;
+    const int64_t n = sd.n;
+    const int64_t chunk = std::min<int64_t>(n, kStageNodes);
+    // geometry: whole rows per chunk
+    const int64_t rows = (int64_t)sd.ny * sd.nz;
+    const int64_t rows_per = std::max<int64_t>(1, chunk / sd.nx);
+    uint32_t* mask = reinterpret_cast<uint32_t*>(ctx->base + sd.mask);
+    for (int64_t r0 = 0; r0 < rows; r0 += rows_per) {
+        const int64_t nr = std::min(rows_per, rows - r0);
+        HIP_TRY(hipMemcpyAsync(stage, in.solid + r0 * sd.nx, (size_t)(nr * sd.nx),
+                               hipMemcpyHostToDevice, ctx->stream));
+        const int64_t nt = nr * sd.words;
+        hipLaunchKernelGGL(k_pack_mask, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0,
+                           ctx->stream, stage, mask, sd.nx, sd.words, r0, nr);
+        HIP_TRY(hipGetLastError());
+        HIP_TRY(hipStreamSynchronize(ctx->stream));
+    }
+    // state
+    for (int64_t i0 = 0; i0 < n; i0 += chunk) {
+        const int64_t len = std::min(chunk, n - i0);
+        uint8_t* st_solid = stage;
+        double* st_d = reinterpret_cast<double*>(stage + align_up((size_t)len, kAlign));
+        double* st_u = st_d + len;
+        HIP_TRY(hipMemcpyAsync(st_solid, in.solid + i0, (size_t)len, hipMemcpyHostToDevice,
+                               ctx->stream));
+        if (in.drho0)
+            HIP_TRY(hipMemcpyAsync(st_d, in.drho0 + i0, sizeof(double) * len,
+                                   hipMemcpyHostToDevice, ctx->stream));
+        if (in.u0)
+            for (int a = 0; a < 3; ++a)
+                HIP_TRY(hipMemcpyAsync(st_u + a * len, in.u0 + (int64_t)a * n + i0,
+                                       sizeof(double) * len, hipMemcpyHostToDevice,
+                                       ctx->stream));
+        hipLaunchKernelGGL(k_upload<P>, dim3((unsigned)((len + 255) / 256)), dim3(256), 0,
+                           ctx->stream, ctx->args[0], s, st_solid, in.drho0 ? st_d : nullptr,
+                           in.u0 ? st_u : nullptr, i0, len);
+        HIP_TRY(hipGetLastError());
+        HIP_TRY(hipStreamSynchronize(ctx->stream));
+    }
+    return TAU1_OK;
+}
+
+tau1_status upload_sample(tau1_ctx* ctx, int s, const tau1_sample& in) {
+    switch (ctx->precision) {
+        case kF64: return upload_sample_t<kF64>(ctx, s, in);
+        case kF32: return upload_sample_t<kF32>(ctx, s, in);
+        case kF16: return upload_sample_t<kF16>(ctx, s, in);
+        case kBF16: return upload_sample_t<kBF16>(ctx, s, in);
+    }
+    return TAU1_E_INVALID;
+}
+
+template <int P>
+tau1_status export_sample_t(tau1_ctx* ctx, int s, double* drho, double* u, int* nbad) {
+    const SampleDev& sd = ctx->plan.s[s].dev;
+    uint8_t* stage = ctx->base + ctx->plan.stage_off;
+    int* bad = reinterpret_cast<int*>(ctx->base + ctx->plan.partial_off +
+                                      sizeof(double) * (kReduceBlocks * 4 + 4));
+    HIP_TRY(hipMemsetAsync(bad, 0, sizeof(int), ctx->stream));
+    const int64_t n = sd.n;
+    const int64_t chunk = std::min<int64_t>(n, kStageNodes);
+    double* out = reinterpret_cast<double*>(stage);
+    for (int64_t i0 = 0; i0 < n; i0 += chunk) {
+        const int64_t len = std::min(chunk, n - i0);
+        hipLaunchKernelGGL(k_export<P>, dim3((unsigned)((len + 255) / 256)), dim3(256), 0,
+                           ctx->stream, ctx->args[ctx->parity], s, out, i0, len, bad);
+        HIP_TRY(hipGetLastError());
+        if (drho)
+            HIP_TRY(hipMemcpyAsync(drho + i0, out, sizeof(double) * len, hipMemcpyDeviceToHost,
+                                   ctx->stream));
+        if (u)
+            for (int a = 0; a < 3; ++a)
+                HIP_TRY(hipMemcpyAsync(u + (int64_t)a * n + i0, out + (1 + a) * len,
+                                       sizeof(double) * len, hipMemcpyDeviceToHost,
+                                       ctx->stream));
+        HIP_TRY(hipStreamSynchronize(ctx->stream));
+    }
+    HIP_TRY(hipMemcpyAsync(nbad, bad, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    return TAU1_OK;
+}
+
+template <int P>
+tau1_status reduce_t(tau1_ctx* ctx, int s, int axis, double out[4]) {
+    const SampleDev& sd = ctx->plan.s[s].dev;
+    double* partial = reinterpret_cast<double*>(ctx->base + ctx->plan.partial_off);
+    double* res = partial + kReduceBlocks * 4;
+    hipLaunchKernelGGL(k_reduce_partial<P>, dim3(kReduceBlocks), dim3(kReduceThreads), 0,
+                       ctx->stream, ctx->args[ctx->parity], s, axis, partial);
+    HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(kReduceThreads), 0, ctx->stream, partial,
+                       sd.n, ctx->g[axis], res);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(out, res, sizeof(double) * 4, hipMemcpyDeviceToHost, ctx->stream));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    return TAU1_OK;
+}
+
+tau1_status check_usable(const tau1_ctx* ctx) {
+    if (!ctx) return TAU1_E_INVALID;
+    if (ctx->sticky != TAU1_OK) return ctx->sticky;
+    return TAU1_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+const char* tau1_strerror(tau1_status s) {
+    switch (s) {
+        case TAU1_OK: return "ok";
+        case TAU1_E_INVALID: return "invalid argument";
+        case TAU1_E_NOMEM: return "host allocation failed";
+        case TAU1_E_HIP: return "HIP runtime or kernel error";
+        case TAU1_E_UNSUPPORTED: return "unsupported configuration";
+        case TAU1_E_NONFINITE: return "non-finite value in state or reduction";
+        case TAU1_E_WORKSPACE: return "workspace missing, too small or misaligned";
+    }
+    return "unknown status";
+}
+
+tau1_status tau1_workspace_size(const tau1_desc* desc, size_t* bytes) {
+    if (!bytes) return TAU1_E_INVALID;
+    const tau1_status v = validate(desc);
+    if (v != TAU1_OK) return v;
+    try {
+        *bytes = make_plan(desc).total;
+    } catch (const std::bad_alloc&) {
+        return TAU1_E_NOMEM;
+    }
+    return TAU1_OK;
+}
+
+tau1_status tau1_create(const tau1_desc* desc, tau1_ctx** out) {
+    if (!out) return TAU1_E_INVALID;
+    *out = nullptr;
+    tau1_status v = validate(desc);
+    if (v != TAU1_OK) return v;
+    // non-finite initial fields are rejected before any GPU work
+    for (int i = 0; i < desc->n_samples; ++i) {
+        const tau1_sample& s = desc->samples[i];
+        const int64_t n = s.nx * s.ny * s.nz;
+        if (s.drho0)
+            for (int64_t j = 0; j < n; ++j)
+                if (!std::isfinite(s.drho0[j]) || s.drho0[j] <= -1.0) return TAU1_E_INVALID;
+        if (s.u0)
+            for (int64_t j = 0; j < 3 * n; ++j)
+                if (!std::isfinite(s.u0[j])) return TAU1_E_INVALID;
+    }
+    if (!desc->workspace) return TAU1_E_WORKSPACE;
+    if (reinterpret_cast<uintptr_t>(desc->workspace) % kAlign != 0) return TAU1_E_WORKSPACE;
+    tau1_ctx* ctx = new (std::nothrow) tau1_ctx();
+    if (!ctx) return TAU1_E_NOMEM;
+    try {
+        ctx->plan = make_plan(desc);
+    } catch (const std::bad_alloc&) {
+        delete ctx;
+        return TAU1_E_NOMEM;
+    }
+    if (desc->workspace_bytes < ctx->plan.total) {
+        delete ctx;
+        return TAU1_E_WORKSPACE;
+    }
+    ctx->lattice = desc->lattice;
+    ctx->precision = desc->precision;
+    ctx->nsamples = desc->n_samples;
+    ctx->graph_chunk = desc->graph_chunk ? desc->graph_chunk : 100;
+    ctx->stream = reinterpret_cast<hipStream_t>(desc->hip_stream);
+    ctx->base = reinterpret_cast<uint8_t*>(desc->workspace);
+    ctx->ws_bytes = desc->workspace_bytes;
+    ctx->cache = desc->tune_cache ? desc->tune_cache : "";
+    for (int a = 0; a < 3; ++a) ctx->g[a] = desc->g[a];
+
+    const int lsr = desc->f16_log2_scale_rho ? desc->f16_log2_scale_rho : 20;
+    const int lsu = desc->f16_log2_scale_u ? desc->f16_log2_scale_u : 20;
+    for (int p = 0; p < 2; ++p) {
+        StepArgs& a = ctx->args[p];
+        std::memset(&a, 0, sizeof a);
+        a.base = ctx->base;
+        a.samples = reinterpret_cast<const SampleDev*>(ctx->base + ctx->plan.samples_off);
+        a.tiles = reinterpret_cast<const int32_t*>(ctx->base + ctx->plan.tiles_off);
+        a.nsamples = ctx->nsamples;
+        a.ntiles = (int32_t)ctx->plan.ntiles;
+        a.parity = p;
+        for (int d = 0; d < 3; ++d) {
+            a.gh[d] = 0.5 * desc->g[d];
+            a.ghf[d] = (float)(0.5 * desc->g[d]);
+        }
+        a.scale_rho = std::ldexp(1.0f, lsr);
+        a.inv_scale_rho = std::ldexp(1.0f, -lsr);
+        a.scale_u = std::ldexp(1.0f, lsu);
+        a.inv_scale_u = std::ldexp(1.0f, -lsu);
+    }
+    // fluid counts (host marshalling of the geometry)
+    for (int i = 0; i < ctx->nsamples; ++i) {
+        const tau1_sample& s = desc->samples[i];
+        const int64_t n = s.nx * s.ny * s.nz;
+        int64_t nf = 0;
+        for (int64_t j = 0; j < n; ++j) nf += s.solid[j] ? 0 : 1;
+        ctx->plan.s[i].n_fluid = nf;
+        ctx->n_fluid += nf;
+        ctx->n_nodes += n;
+    }
+    // descriptors and work list
+    std::vector<SampleDev> sdev(ctx->nsamples);
+    for (int i = 0; i < ctx->nsamples; ++i) sdev[i] = ctx->plan.s[i].dev;
+    tau1_status st = TAU1_OK;
+    {
+        hipError_t e = hipMemcpyAsync(ctx->base + ctx->plan.samples_off, sdev.data(),
+                                      sizeof(SampleDev) * sdev.size(), hipMemcpyHostToDevice,
+                                      ctx->stream);
+        if (e == hipSuccess) {
+            std::vector<int32_t> tl = zmarch_worklist(ctx->plan.s.data(), ctx->nsamples,
+                                                      ctx->plan.ntiles);
+            if (!tl.empty())
+                e = hipMemcpyAsync(ctx->base + ctx->plan.tiles_off, tl.data(),
+                                   sizeof(int32_t) * tl.size(), hipMemcpyHostToDevice,
+                                   ctx->stream);
+            if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+        }
+        if (e != hipSuccess) st = fail_hip(ctx, e);
+    }
+    for (int i = 0; st == TAU1_OK && i < ctx->nsamples; ++i)
+        st = upload_sample(ctx, i, desc->samples[i]);
+    if (st != TAU1_OK) {
+        delete ctx;
+        return st;
+    }
+    // kernel choice: explicit, else tuned cache, else the default
+    const bool zm = zmarch_eligible(ctx);
+    if (desc->kernel == 1 && !zm) {
+        delete ctx;
+        return TAU1_E_UNSUPPORTED;
+    }
+    ctx->kernel = desc->kernel >= 0 ? desc->kernel : (zm ? 1 : 0);
+    ctx->tile = desc->tile >= 0 ? desc->tile : zmarch_default_tile(ctx->lattice, ctx->precision);
+    if (ctx->kernel == 1 && desc->tile < 0 && !ctx->cache.empty()) {
+        int t = zmarch_cache_lookup(ctx->cache.c_str(), ctx->lattice, ctx->precision,
+                                    ctx->n_nodes);
+        if (t >= 0) ctx->tile = t;
+    }
+    *out = ctx;
+    return TAU1_OK;
+}
+
+tau1_status tau1_step(tau1_ctx* ctx, int64_t nsteps) {
+    tau1_status st = check_usable(ctx);
+    if (st != TAU1_OK) return st;
+    if (nsteps < 0) return TAU1_E_INVALID;
+    if (nsteps >= ctx->graph_chunk) {
+        if (!ctx->exec || ctx->graph_kernel != ctx->kernel || ctx->graph_tile != ctx->tile ||
+            ctx->graph_parity != ctx->parity) {
+            st = build_graph(ctx);
+            if (st != TAU1_OK) return st;
+        }
+        while (nsteps >= ctx->graph_chunk) {
+            HIP_TRY(hipGraphLaunch(ctx->exec, ctx->stream));
+            nsteps -= ctx->graph_chunk;
+            ctx->steps_done += ctx->graph_chunk;
+        }
+    }
+    while (nsteps > 0) {
+        st = launch_one(ctx, ctx->kernel, ctx->tile, ctx->args[ctx->parity]);
+        if (st != TAU1_OK) return st;
+        ctx->parity ^= 1;
+        --nsteps;
+        ++ctx->steps_done;
+    }
+    return TAU1_OK;
+}
+
+tau1_status tau1_sync(tau1_ctx* ctx) {
+    tau1_status st = check_usable(ctx);
+    if (st != TAU1_OK) return st;
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    HIP_TRY(hipGetLastError());
+    return TAU1_OK;
+}
+
+tau1_status tau1_moments(tau1_ctx* ctx, int32_t sample, double* drho, double* u) {
+    tau1_status st = check_usable(ctx);
+    if (st != TAU1_OK) return st;
+    if (sample < 0 || sample >= ctx->nsamples) return TAU1_E_INVALID;
+    int nbad = 0;
+    switch (ctx->precision) {
+        case kF64: st = export_sample_t<kF64>(ctx, sample, drho, u, &nbad); break;
+        case kF32: st = export_sample_t<kF32>(ctx, sample, drho, u, &nbad); break;
+        case kF16: st = export_sample_t<kF16>(ctx, sample, drho, u, &nbad); break;
+        case kBF16: st = export_sample_t<kBF16>(ctx, sample, drho, u, &nbad); break;
+    }
+    if (st != TAU1_OK) return st;
+    return nbad ? TAU1_E_NONFINITE : TAU1_OK;
+}
+
+tau1_status tau1_permeability(tau1_ctx* ctx, int32_t sample, int32_t axis, double* k,
+                              double* mass) {
+    tau1_status st = check_usable(ctx);
+    if (st != TAU1_OK) return st;
+    if (sample < 0 || sample >= ctx->nsamples || axis < 0 || axis > 2) return TAU1_E_INVALID;
+    if (k && ctx->g[axis] == 0.0) return TAU1_E_INVALID;
+    double res[4] = {0, 0, 0, 0};
+    switch (ctx->precision) {
+        case kF64: st = reduce_t<kF64>(ctx, sample, axis, res); break;
+        case kF32: st = reduce_t<kF32>(ctx, sample, axis, res); break;
+        case kF16: st = reduce_t<kF16>(ctx, sample, axis, res); break;
+        case kBF16: st = reduce_t<kBF16>(ctx, sample, axis, res); break;
+    }
+    if (st != TAU1_OK) return st;
+    if (res[3] != 0.0 || !std::isfinite(res[0]) || !std::isfinite(res[1]))
+        return TAU1_E_NONFINITE;
+    if (k) *k = res[1];
+    if (mass) *mass = res[0];
+    return TAU1_OK;
+}
+
+tau1_status tau1_autotune(tau1_ctx* ctx, int32_t trial_steps) {
+    tau1_status st = check_usable(ctx);
+    if (st != TAU1_OK) return st;
+    if (trial_steps < 1) return TAU1_E_INVALID;
+    if (!zmarch_eligible(ctx)) return TAU1_OK;  // only the gather kernel applies
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    float best = 1e30f;
+    int best_tile = ctx->tile;
+    for (int t = 0; t < kNumTiles; ++t) {
+        if (!zmarch_tile_ok(ctx->lattice, ctx->precision, t)) continue;
+        // the trial reads the current buffer and writes the spare one only
+        st = launch_one(ctx, 1, t, ctx->args[ctx->parity]);
+        if (st != TAU1_OK) break;
+        HIP_TRY(hipEventRecord(e0, ctx->stream));
+        for (int i = 0; i < trial_steps && st == TAU1_OK; ++i)
+            st = launch_one(ctx, 1, t, ctx->args[ctx->parity]);
+        HIP_TRY(hipEventRecord(e1, ctx->stream));
+        HIP_TRY(hipEventSynchronize(e1));
+        float ms = 0;
+        HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+        if (ms < best) {
+            best = ms;
+            best_tile = t;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != TAU1_OK) return st;
+    ctx->kernel = 1;
+    ctx->tile = best_tile;
+    if (!ctx->cache.empty())
+        zmarch_cache_store(ctx->cache.c_str(), ctx->lattice, ctx->precision, ctx->n_nodes,
+                           best_tile, best / trial_steps);
+    return TAU1_OK;
+}
+
+tau1_status tau1_get_info(const tau1_ctx* ctx, tau1_info* info) {
+    if (!ctx || !info) return TAU1_E_INVALID;
+    info->lattice = ctx->lattice;
+    info->precision = ctx->precision;
+    info->n_samples = ctx->nsamples;
+    info->kernel = ctx->kernel;
+    info->tile = ctx->tile;
+    info->graph_chunk = ctx->graph_chunk;
+    info->n_nodes = ctx->n_nodes;
+    info->n_fluid = ctx->n_fluid;
+    info->steps_done = ctx->steps_done;
+    const double s = storage_bytes(ctx->precision);
+    info->bytes_per_step = 2.0 * 4.0 * s * (double)ctx->n_fluid + (double)ctx->n_nodes / 8.0;
+    return TAU1_OK;
+}
+
+void tau1_destroy(tau1_ctx* ctx) {
+    if (!ctx) return;
+    destroy_graph(ctx);
+    delete ctx;
+}
+
+tau1_status tau1_copy_probe(void* hip_stream, void* buf, size_t bytes, int32_t reps,
+                            double* seconds) {
+    if (!buf || bytes < 64 || reps < 1 || !seconds) return TAU1_E_INVALID;
+    tau1_ctx* ctx = nullptr;
+    hipStream_t stream = reinterpret_cast<hipStream_t>(hip_stream);
+    const int64_t n = (int64_t)(bytes / 2 / 16);
+    const float4* src = reinterpret_cast<const float4*>(buf);
+    float4* dst = reinterpret_cast<float4*>(reinterpret_cast<uint8_t*>(buf) + n * 16);
+    int dev = 0, cus = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    const unsigned grid = (unsigned)std::min<int64_t>((n + 255) / 256, (int64_t)cus * 16);
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    hipLaunchKernelGGL(k_copy16, dim3(grid), dim3(256), 0, stream, src, dst, n);
+    HIP_TRY(hipEventRecord(e0, stream));
+    for (int r = 0; r < reps; ++r)
+        hipLaunchKernelGGL(k_copy16, dim3(grid), dim3(256), 0, stream, src, dst, n);
+    HIP_TRY(hipEventRecord(e1, stream));
+    HIP_TRY(hipEventSynchronize(e1));
+    float ms = 0;
+    HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    *seconds = ms * 1e-3 / reps;
+    return TAU1_OK;
+}
+
+}  // extern "C"

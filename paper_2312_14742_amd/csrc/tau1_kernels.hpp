@@ -1,0 +1,296 @@
+// tau1_kernels.hpp -- per-node gather step kernel and the service kernels
+// (geometry encode, state upload/readback, FP64 reductions, copy probe).
+#pragma once
+
+#include "tau1_device.hpp"
+
+namespace tau1 {
+
+// Arguments shared by every step kernel (passed by value; one copy per
+// ping-pong parity is kept by the host so HIP graph nodes can point at it).
+struct StepArgs {
+    uint8_t* base;              // workspace base
+    const SampleDev* samples;   // device array, nsamples entries
+    const int32_t* tiles;       // z-march work list (sample, ty, tz) triples
+    int32_t nsamples;
+    int32_t parity;             // buffer read this step; the other is written
+    int32_t ntiles;             // z-march work items
+    int32_t pad;
+    double gh[3];               // g / 2 (FP64)
+    float ghf[3];               // g / 2 (FP32)
+    float scale_rho, inv_scale_rho, scale_u, inv_scale_u;  // F16 storage
+};
+
+template <int P>
+__device__ __forceinline__ typename Storage<P>::T inv_scale_rho(const StepArgs& a) {
+    if constexpr (P == kF16) return a.inv_scale_rho; else return 1;
+}
+template <int P>
+__device__ __forceinline__ typename Storage<P>::T inv_scale_u(const StepArgs& a) {
+    if constexpr (P == kF16) return a.inv_scale_u; else return 1;
+}
+template <int P>
+__device__ __forceinline__ typename Storage<P>::T scale_rho(const StepArgs& a) {
+    if constexpr (P == kF16) return a.scale_rho; else return 1;
+}
+template <int P>
+__device__ __forceinline__ typename Storage<P>::T scale_u(const StepArgs& a) {
+    if constexpr (P == kF16) return a.scale_u; else return 1;
+}
+template <typename T>
+__device__ __forceinline__ T gh_of(const StepArgs& a, int d) {
+    if constexpr (sizeof(T) == 8) return a.gh[d]; else return a.ghf[d];
+}
+
+// Sample owning a block of a per-node launch (samples sorted by block0).
+__device__ __forceinline__ int sample_of_block(const SampleDev* s, int n, int64_t b) {
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (s[mid].block0 <= b) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+constexpr int kGatherBlock = 256;
+
+// ---------------------------------------------------------------------------
+// Per-node gather step (pull form).  One thread per node; the node reads the
+// pre-step (drho, v) of each source x - c_k (periodic wrap, then the solid
+// test), forms the equilibrium of Eq. (3) minus its weight and accumulates
+// density and momentum in direction order; a solid source is replaced by the
+// node's own state with the opposite direction (halfway bounce-back, Eq. (11)).
+// One reciprocal per node (division-saving algorithm).  Contraction into FMA
+// is disabled so the FP64 instance reproduces plain IEEE evaluation.
+// ---------------------------------------------------------------------------
+template <int Q, int P>
+__global__ __launch_bounds__(kGatherBlock) void k_gather(StepArgs a) {
+#pragma clang fp contract(off)
+    using St = Storage<P>;
+    using S = typename St::S;
+    using T = typename St::T;
+    using L = Lattice<Q>;
+    const int s = sample_of_block(a.samples, a.nsamples, blockIdx.x);
+    const SampleDev& sd = a.samples[s];
+    const int64_t i = (int64_t)(blockIdx.x - sd.block0) * kGatherBlock + threadIdx.x;
+    if (i >= sd.n) return;
+    const int nx = sd.nx, ny = sd.ny, nz = sd.nz;
+    const int x = (int)(i % nx);
+    const int y = (int)((i / nx) % ny);
+    const int z = (int)(i / ((int64_t)nx * ny));
+    const uint32_t* mask = reinterpret_cast<const uint32_t*>(a.base + sd.mask);
+    if (solid_bit(mask, sd.words, ny, x, y, z)) return;
+
+    const S* pre = reinterpret_cast<const S*>(a.base + sd.state[a.parity]);
+    S* post = reinterpret_cast<S*>(a.base + sd.state[a.parity ^ 1]);
+    const int64_t st = sd.stride;
+    const T isr = inv_scale_rho<P>(a), isu = inv_scale_u<P>(a);
+    const T d0 = St::load(pre, i, isr);
+    const T v0x = St::load(pre + st, i, isu);
+    const T v0y = St::load(pre + 2 * st, i, isu);
+    const T v0z = St::load(pre + 3 * st, i, isu);
+
+    T d = 0, jx = 0, jy = 0, jz = 0;
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+        const int cx = L::c[k].x, cy = L::c[k].y, cz = L::c[k].z;
+        int sx = x - cx, sy = y - cy, sz = z - cz;
+        sx += sx < 0 ? nx : 0; sx -= sx >= nx ? nx : 0;
+        sy += sy < 0 ? ny : 0; sy -= sy >= ny ? ny : 0;
+        sz += sz < 0 ? nz : 0; sz -= sz >= nz ? nz : 0;
+        T ds, vx, vy, vz, ex, ey, ez;
+        if (!solid_bit(mask, sd.words, ny, sx, sy, sz)) {
+            const int64_t j = sx + (int64_t)nx * (sy + (int64_t)ny * sz);
+            ds = St::load(pre, j, isr);
+            vx = St::load(pre + st, j, isu);
+            vy = St::load(pre + 2 * st, j, isu);
+            vz = St::load(pre + 3 * st, j, isu);
+            ex = (T)cx; ey = (T)cy; ez = (T)cz;
+        } else {
+            ds = d0; vx = v0x; vy = v0y; vz = v0z;
+            ex = (T)-cx; ey = (T)-cy; ez = (T)-cz;
+        }
+        const T rho = (T)1 + ds;
+        const T cu = (ex * vx + ey * vy) + ez * vz;
+        const T vv = (vx * vx + vy * vy) + vz * vz;
+        const T p = ((T)3 * cu + ((T)4.5 * cu) * cu) - (T)1.5 * vv;
+        const T f = (T)weight<Q>(k) * (ds + rho * p);
+        d += f;
+        jx += (T)cx * f;
+        jy += (T)cy * f;
+        jz += (T)cz * f;
+    }
+    const T r = (T)1 / ((T)1 + d);
+    const T ghx = gh_of<T>(a, 0), ghy = gh_of<T>(a, 1), ghz = gh_of<T>(a, 2);
+    const T ux = jx * r + ghx, uy = jy * r + ghy, uz = jz * r + ghz;
+    const T sr = scale_rho<P>(a), su = scale_u<P>(a);
+    St::store(post, i, d, sr);
+    St::store(post + st, i, ux + ghx, su);
+    St::store(post + 2 * st, i, uy + ghy, su);
+    St::store(post + 3 * st, i, uz + ghz, su);
+}
+
+// ---------------------------------------------------------------------------
+// Geometry encode (a0): pack solid bytes of rows [row0, row0 + nrows) into
+// 32-node words; one thread per word.  Rows are (y, z) pairs, row = y + ny z.
+// ---------------------------------------------------------------------------
+__global__ void k_pack_mask(const uint8_t* __restrict__ solid, uint32_t* __restrict__ mask,
+                            int nx, int words, int64_t row0, int64_t nrows) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nrows * words) return;
+    const int64_t r = t / words;
+    const int w = (int)(t % words);
+    const uint8_t* src = solid + r * nx;
+    uint32_t bits = 0;
+    const int x0 = w * 32;
+    const int x1 = min(x0 + 32, nx);
+    for (int x = x0; x < x1; ++x) bits |= (src[x] != 0 ? 1u : 0u) << (x - x0);
+    mask[(row0 + r) * words + w] = bits;
+}
+
+// State upload: staging FP64 (drho0, u0) for nodes [i0, i0 + len) of one
+// sample into both buffers; v = u + g/2; solid nodes get exact zeros.
+template <int P>
+__global__ void k_upload(StepArgs a, int s, const uint8_t* __restrict__ solid,
+                         const double* __restrict__ drho0, const double* __restrict__ u0,
+                         int64_t i0, int64_t len) {
+    using St = Storage<P>;
+    using S = typename St::S;
+    using T = typename St::T;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= len) return;
+    const SampleDev& sd = a.samples[s];
+    const int64_t i = i0 + t;
+    T d = 0, vx = 0, vy = 0, vz = 0;
+    if (!solid[t]) {
+        // widen/narrow from FP64 in the compute type, then add g/2 there
+        d = drho0 ? (T)drho0[t] : (T)0;
+        vx = (u0 ? (T)u0[t] : (T)0) + gh_of<T>(a, 0);
+        vy = (u0 ? (T)u0[len + t] : (T)0) + gh_of<T>(a, 1);
+        vz = (u0 ? (T)u0[2 * len + t] : (T)0) + gh_of<T>(a, 2);
+    }
+    const T sr = scale_rho<P>(a), su = scale_u<P>(a);
+    for (int b = 0; b < 2; ++b) {
+        S* p = reinterpret_cast<S*>(a.base + sd.state[b]);
+        St::store(p, i, d, sr);
+        St::store(p + sd.stride, i, vx, su);
+        St::store(p + 2 * sd.stride, i, vy, su);
+        St::store(p + 3 * sd.stride, i, vz, su);
+    }
+}
+
+// State readback: nodes [i0, i0 + len) of one sample, current buffer, into
+// FP64 staging (drho | ux | uy | uz, each len values); u = v - g/2 in FP64;
+// solid nodes read 0.  Counts non-finite fluid values into *bad.
+template <int P>
+__global__ void k_export(StepArgs a, int s, double* __restrict__ out, int64_t i0,
+                         int64_t len, int* bad) {
+    using St = Storage<P>;
+    using S = typename St::S;
+    using T = typename St::T;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= len) return;
+    const SampleDev& sd = a.samples[s];
+    const int64_t i = i0 + t;
+    const int x = (int)(i % sd.nx);
+    const int y = (int)((i / sd.nx) % sd.ny);
+    const int z = (int)(i / ((int64_t)sd.nx * sd.ny));
+    const uint32_t* mask = reinterpret_cast<const uint32_t*>(a.base + sd.mask);
+    double d = 0, ux = 0, uy = 0, uz = 0;
+    if (!solid_bit(mask, sd.words, sd.ny, x, y, z)) {
+        const S* p = reinterpret_cast<const S*>(a.base + sd.state[a.parity]);
+        d = (double)St::load(p, i, inv_scale_rho<P>(a));
+        ux = (double)St::load(p + sd.stride, i, inv_scale_u<P>(a)) - a.gh[0];
+        uy = (double)St::load(p + 2 * sd.stride, i, inv_scale_u<P>(a)) - a.gh[1];
+        uz = (double)St::load(p + 3 * sd.stride, i, inv_scale_u<P>(a)) - a.gh[2];
+        if (!isfinite(d) || !isfinite(ux) || !isfinite(uy) || !isfinite(uz))
+            atomicAdd(bad, 1);
+    }
+    out[t] = d;
+    out[len + t] = ux;
+    out[2 * len + t] = uy;
+    out[3 * len + t] = uz;
+}
+
+// ---------------------------------------------------------------------------
+// FP64 reductions (a6), deterministic: block b owns the contiguous node range
+// [b*chunk, (b+1)*chunk); each thread sums its strided sub-sequence in order,
+// then the block combines in a fixed tree.  Partials: (sum drho, sum u_axis,
+// fluid count, non-finite count) per block.
+// ---------------------------------------------------------------------------
+constexpr int kReduceBlocks = 1024;
+constexpr int kReduceThreads = 256;
+
+template <int P>
+__global__ __launch_bounds__(kReduceThreads) void k_reduce_partial(StepArgs a, int s, int axis,
+                                                                   double* __restrict__ partial) {
+    using St = Storage<P>;
+    using S = typename St::S;
+    const SampleDev& sd = a.samples[s];
+    const int64_t chunk = (sd.n + kReduceBlocks - 1) / kReduceBlocks;
+    const int64_t beg = (int64_t)blockIdx.x * chunk;
+    const int64_t end = min(beg + chunk, sd.n);
+    const uint32_t* mask = reinterpret_cast<const uint32_t*>(a.base + sd.mask);
+    const S* p = reinterpret_cast<const S*>(a.base + sd.state[a.parity]);
+    const S* pu = p + (int64_t)(1 + axis) * sd.stride;
+    double sdr = 0, su = 0, nf = 0, nb = 0;
+    for (int64_t i = beg + threadIdx.x; i < end; i += kReduceThreads) {
+        const int x = (int)(i % sd.nx);
+        const int y = (int)((i / sd.nx) % sd.ny);
+        const int z = (int)(i / ((int64_t)sd.nx * sd.ny));
+        if (solid_bit(mask, sd.words, sd.ny, x, y, z)) continue;
+        const double d = (double)St::load(p, i, inv_scale_rho<P>(a));
+        const double u = (double)St::load(pu, i, inv_scale_u<P>(a)) - a.gh[axis];
+        if (!isfinite(d) || !isfinite(u)) { nb += 1; continue; }
+        sdr += d;
+        su += u;
+        nf += 1;
+    }
+    __shared__ double sh[4][kReduceThreads];
+    sh[0][threadIdx.x] = sdr;
+    sh[1][threadIdx.x] = su;
+    sh[2][threadIdx.x] = nf;
+    sh[3][threadIdx.x] = nb;
+    __syncthreads();
+    for (int w = kReduceThreads / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+            for (int c = 0; c < 4; ++c) sh[c][threadIdx.x] += sh[c][threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x < 4) partial[blockIdx.x * 4 + threadIdx.x] = sh[threadIdx.x][0];
+}
+
+// Final pass over the kReduceBlocks partials (one block, fixed tree); writes
+// out[0] = mass, out[1] = permeability (or 0 when g_axis == 0), out[2] = fluid
+// count, out[3] = non-finite count.
+__global__ __launch_bounds__(kReduceThreads) void k_reduce_final(const double* __restrict__ partial,
+                                                                 int64_t n, double g_axis,
+                                                                 double* __restrict__ out) {
+    __shared__ double sh[4][kReduceThreads];
+    double acc[4] = {0, 0, 0, 0};
+    for (int b = threadIdx.x; b < kReduceBlocks; b += kReduceThreads)
+        for (int c = 0; c < 4; ++c) acc[c] += partial[b * 4 + c];
+    for (int c = 0; c < 4; ++c) sh[c][threadIdx.x] = acc[c];
+    __syncthreads();
+    for (int w = kReduceThreads / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+            for (int c = 0; c < 4; ++c) sh[c][threadIdx.x] += sh[c][threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double sum_drho = sh[0][0], sum_u = sh[1][0], nf = sh[2][0];
+        out[0] = nf + sum_drho;
+        out[1] = g_axis != 0.0 ? (1.0 / 6.0) * (sum_u / (double)n) / g_axis : 0.0;
+        out[2] = nf;
+        out[3] = sh[3][0];
+    }
+}
+
+// Copy probe: 16-byte vector copy, grid-stride.
+__global__ void k_copy16(const float4* __restrict__ src, float4* __restrict__ dst, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = src[i];
+}
+
+}  // namespace tau1
