@@ -93,10 +93,9 @@ Plan make_plan(const tau1_desc* d) {
         sd.block0 = blocks;
         blocks += (sd.n + kGatherBlock - 1) / kGatherBlock;
         zmarch_tiling(sd);
-        sd.tile0 = tiles;
-        tiles += (int64_t)sd.tiles_y * sd.tiles_z;
         maxn = std::max<int64_t>(maxn, sd.n);
     }
+    tiles = zmarch_max_items(p.s.data(), d->n_samples);
     p.total_blocks = blocks;
     p.ntiles = tiles;
     p.tiles_off = off;
@@ -105,6 +104,8 @@ Plan make_plan(const tau1_desc* d) {
         SampleDev& sd = p.s[i].dev;
         sd.mask = (int64_t)off;
         off = align_up(off + sizeof(uint32_t) * (size_t)sd.words * sd.ny * sd.nz, kAlign);
+        sd.xmask = (int64_t)off;
+        off = align_up(off + sizeof(uint32_t) * ((size_t)sd.xwords * sd.ny * sd.nz + 2), kAlign);
         for (int b = 0; b < 2; ++b) {
             sd.state[b] = (int64_t)off;
             off = align_up(off + (size_t)4 * sd.stride * sz, kAlign);
@@ -198,7 +199,7 @@ Launch step_launch(const tau1_ctx* ctx, int kernel, int tile) {
     if (kernel == 1) {
         l.fn = pick_zmarch(ctx->lattice, ctx->precision, tile);
         l.block = dim3(zmarch_threads(tile));
-        l.grid = dim3((unsigned)zmarch_grid(ctx->plan.ntiles, tile));
+        l.grid = dim3((unsigned)zmarch_grid(ctx->args[0].ntiles, tile));
         l.shmem = 0;
     } else {
         l.fn = pick_gather(ctx->lattice, ctx->precision);
@@ -274,6 +275,15 @@ tau1_status upload_sample_t(tau1_ctx* ctx, int s, const tau1_sample& in) {
         hipLaunchKernelGGL(k_pack_mask, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0,
                            ctx->stream, stage, mask, sd.nx, sd.words, r0, nr);
         HIP_TRY(hipGetLastError());
+        HIP_TRY(hipStreamSynchronize(ctx->stream));
+    }
+    {
+        const int64_t nt = rows * sd.xwords;
+        uint32_t* xm = reinterpret_cast<uint32_t*>(ctx->base + sd.xmask);
+        hipLaunchKernelGGL(k_build_xmask, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0,
+                           ctx->stream, mask, xm, sd.nx, sd.words, sd.xwords, rows);
+        HIP_TRY(hipGetLastError());
+        HIP_TRY(hipMemsetAsync(xm + nt, 0, 2 * sizeof(uint32_t), ctx->stream));
         HIP_TRY(hipStreamSynchronize(ctx->stream));
     }
     // state
@@ -354,6 +364,23 @@ tau1_status reduce_t(tau1_ctx* ctx, int s, int axis, double out[4]) {
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipMemcpyAsync(out, res, sizeof(double) * 4, hipMemcpyDeviceToHost, ctx->stream));
     HIP_TRY(hipStreamSynchronize(ctx->stream));
+    return TAU1_OK;
+}
+
+// Selects the z-march tile (z-segment length), rebuilds and uploads the work
+// list; cached graphs are rebuilt on the next step.
+tau1_status set_tile(tau1_ctx* ctx, int tile) {
+    std::vector<int32_t> tl = zmarch_worklist(ctx->plan.s.data(), ctx->nsamples, kTileLZ[tile]);
+    const int64_t items = (int64_t)tl.size() / 4;
+    if (items > ctx->plan.ntiles) return TAU1_E_INVALID;
+    if (!tl.empty()) {
+        HIP_TRY(hipMemcpyAsync(ctx->base + ctx->plan.tiles_off, tl.data(),
+                               sizeof(int32_t) * tl.size(), hipMemcpyHostToDevice, ctx->stream));
+        HIP_TRY(hipStreamSynchronize(ctx->stream));
+    }
+    ctx->args[0].ntiles = ctx->args[1].ntiles = (int32_t)items;
+    ctx->tile = tile;
+    destroy_graph(ctx);
     return TAU1_OK;
 }
 
@@ -465,7 +492,7 @@ tau1_status tau1_create(const tau1_desc* desc, tau1_ctx** out) {
         ctx->n_fluid += nf;
         ctx->n_nodes += n;
     }
-    // descriptors and work list
+    // descriptors
     std::vector<SampleDev> sdev(ctx->nsamples);
     for (int i = 0; i < ctx->nsamples; ++i) sdev[i] = ctx->plan.s[i].dev;
     tau1_status st = TAU1_OK;
@@ -473,15 +500,7 @@ tau1_status tau1_create(const tau1_desc* desc, tau1_ctx** out) {
         hipError_t e = hipMemcpyAsync(ctx->base + ctx->plan.samples_off, sdev.data(),
                                       sizeof(SampleDev) * sdev.size(), hipMemcpyHostToDevice,
                                       ctx->stream);
-        if (e == hipSuccess) {
-            std::vector<int32_t> tl = zmarch_worklist(ctx->plan.s.data(), ctx->nsamples,
-                                                      ctx->plan.ntiles);
-            if (!tl.empty())
-                e = hipMemcpyAsync(ctx->base + ctx->plan.tiles_off, tl.data(),
-                                   sizeof(int32_t) * tl.size(), hipMemcpyHostToDevice,
-                                   ctx->stream);
-            if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
-        }
+        if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
         if (e != hipSuccess) st = fail_hip(ctx, e);
     }
     for (int i = 0; st == TAU1_OK && i < ctx->nsamples; ++i)
@@ -497,11 +516,20 @@ tau1_status tau1_create(const tau1_desc* desc, tau1_ctx** out) {
         return TAU1_E_UNSUPPORTED;
     }
     ctx->kernel = desc->kernel >= 0 ? desc->kernel : (zm ? 1 : 0);
-    ctx->tile = desc->tile >= 0 ? desc->tile : zmarch_default_tile(ctx->lattice, ctx->precision);
+    int tile = desc->tile >= 0 ? desc->tile : zmarch_default_tile(ctx->lattice, ctx->precision);
     if (ctx->kernel == 1 && desc->tile < 0 && !ctx->cache.empty()) {
         int t = zmarch_cache_lookup(ctx->cache.c_str(), ctx->lattice, ctx->precision,
                                     ctx->n_nodes);
-        if (t >= 0) ctx->tile = t;
+        if (t >= 0) tile = t;
+    }
+    if (zm) {
+        st = set_tile(ctx, tile);
+        if (st != TAU1_OK) {
+            delete ctx;
+            return st;
+        }
+    } else {
+        ctx->tile = tile;
     }
     *out = ctx;
     return TAU1_OK;
@@ -589,6 +617,8 @@ tau1_status tau1_autotune(tau1_ctx* ctx, int32_t trial_steps) {
     int best_tile = ctx->tile;
     for (int t = 0; t < kNumTiles; ++t) {
         if (!zmarch_tile_ok(ctx->lattice, ctx->precision, t)) continue;
+        st = set_tile(ctx, t);
+        if (st != TAU1_OK) break;
         // the trial reads the current buffer and writes the spare one only
         st = launch_one(ctx, 1, t, ctx->args[ctx->parity]);
         if (st != TAU1_OK) break;
@@ -608,7 +638,8 @@ tau1_status tau1_autotune(tau1_ctx* ctx, int32_t trial_steps) {
     (void)hipEventDestroy(e1);
     if (st != TAU1_OK) return st;
     ctx->kernel = 1;
-    ctx->tile = best_tile;
+    st = set_tile(ctx, best_tile);
+    if (st != TAU1_OK) return st;
     if (!ctx->cache.empty())
         zmarch_cache_store(ctx->cache.c_str(), ctx->lattice, ctx->precision, ctx->n_nodes,
                            best_tile, best / trial_steps);

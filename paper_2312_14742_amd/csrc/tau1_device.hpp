@@ -126,11 +126,13 @@ struct SampleDev {
     int64_t state[2];     // byte offsets of buffer 0 and buffer 1
     int64_t mask;         // byte offset of the bit mask (uint32 words)
     int64_t block0;       // first block of this sample in a per-node launch
-    int64_t tile0;        // first tile of this sample in a z-march launch
+    int64_t xmask;        // byte offset of the extended (periodic) row mask
     int32_t nx, ny, nz;
     int32_t words;        // mask words per (y, z) row: ceil(nx / 32)
-    int32_t tiles_y, tiles_z;  // z-march tiling of this sample
-    int32_t pad0, pad1;
+    int32_t xwords;       // extended-mask words per row
+    int32_t variant;      // z-march lane layout (-1: not supported)
+    int32_t tiles_y;      // z-march row groups
+    int32_t pad0;
 };
 
 // Solid bit of node (x, y, z).

@@ -1,0 +1,143 @@
+"""Parity of the z-march step kernel (kernel=1) with the FP64 oracle, its
+invariances, and its edge cases (lane layouts, ragged row groups, short
+z-segments, periodic wrap onto itself)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2312_14742_amd import inputs, tau1
+
+from gpu_helpers import reduced_errors, run_gpu, run_oracle
+
+pytestmark = pytest.mark.gpu
+
+UNIT_ROUNDOFF = {"f32": 2.0 ** -24, "f16": 2.0 ** -11, "bf16": 2.0 ** -8}
+
+
+def bounds(prec, u_scale):
+    eps = UNIT_ROUNDOFF[prec]
+    return {"drho_abs": (2.0 * eps + 16.0 * 2.0 ** -24) * u_scale, "u_rel_l2": 8.0 * eps}
+
+
+# nx values cover every lane layout: 64/G lanes per row x PX nodes per lane
+LAYOUT_DIMS = [
+    (64, 5, 7),     # G=1 PX=1
+    (128, 3, 4),    # G=1 PX=2
+    (192, 2, 3),    # G=1 PX=3
+    (256, 3, 2),    # G=1 PX=4
+    (320, 2, 2),    # G=1 PX=5
+    (512, 2, 3),    # G=1 PX=8
+    (32, 9, 4),     # G=2 PX=1
+    (96, 5, 5),     # G=2 PX=3
+    (160, 3, 3),    # G=2 PX=5
+    (224, 3, 2),    # G=2 PX=7
+    (288, 3, 2),    # G=2 PX=9
+    (16, 6, 5),     # G=4 PX=1
+    (48, 7, 3),     # G=4 PX=3
+]
+
+
+@pytest.mark.parametrize("dims", LAYOUT_DIMS)
+@pytest.mark.parametrize("q", [15, 19, 27])
+def test_layouts_f32(q, dims):
+    nx, ny, nz = dims
+    solid, drho, u = inputs.random_state(nx, ny, nz, seed=5000 + nx + 3 * ny + 7 * nz)
+    g = (1e-5, -2e-5, 3e-6)
+    print(f"[case] zmarch f32 q={q} dims={dims}", flush=True)
+    sim, out = run_gpu([(solid, drho, u)], q, "f32", g, 6, kernel=1)
+    assert sim.info()["kernel"] == 1
+    ref = run_oracle(q, solid, drho, u, g, 6)
+    err = reduced_errors(out[0], ref, solid)
+    print(f"[err] {err}", flush=True)
+    for key, b in bounds("f32", np.abs(u).max()).items():
+        assert err[key] <= b, (key, err[key], b)
+    sim.close()
+
+
+@pytest.mark.parametrize("prec", ["f16", "bf16"])
+@pytest.mark.parametrize("dims", [(64, 5, 7), (96, 5, 5), (48, 7, 3)])
+def test_layouts_16bit(prec, dims):
+    nx, ny, nz = dims
+    solid, drho, u = inputs.random_state(nx, ny, nz, seed=6000 + nx + ny)
+    g = (1e-5, -2e-5, 3e-6)
+    print(f"[case] zmarch {prec} dims={dims}", flush=True)
+    sim, out = run_gpu([(solid, drho, u)], 19, prec, g, 6, kernel=1, f16_scales=(18, 18))
+    ref = run_oracle(19, solid, drho, u, g, 6)
+    err = reduced_errors(out[0], ref, solid)
+    print(f"[err] {err}", flush=True)
+    for key, b in bounds(prec, np.abs(u).max()).items():
+        assert err[key] <= b, (key, err[key], b)
+    sim.close()
+
+
+@pytest.mark.parametrize("dims", [(64, 1, 1), (32, 1, 3), (16, 2, 1), (64, 3, 2), (32, 5, 1)])
+def test_degenerate_periodic(dims):
+    """ny or nz of 1-3: the stencil wraps onto the node's own row/plane."""
+    nx, ny, nz = dims
+    solid, drho, u = inputs.random_state(nx, ny, nz, seed=77 + nx * ny * nz)
+    g = (1e-5, 3e-6, -2e-6)
+    print(f"[case] zmarch degenerate dims={dims}", flush=True)
+    sim, out = run_gpu([(solid, drho, u)], 19, "f32", g, 5, kernel=1)
+    ref = run_oracle(19, solid, drho, u, g, 5)
+    err = reduced_errors(out[0], ref, solid)
+    for key, b in bounds("f32", np.abs(u).max()).items():
+        assert err[key] <= b, (key, err[key], b)
+    sim.close()
+
+
+def test_tile_shapes_bitwise_identical():
+    """Every z-segment length gives the same bits (fixed per-node order)."""
+    geo = inputs.spheres(64, 20, 70, 5.0, 0.7, seed=12)
+    g = (1e-5, 0, 0)
+    outs = []
+    for tile in range(4):
+        print(f"[case] tile {tile}", flush=True)
+        sim, out = run_gpu([(geo.solid,)], 19, "f32", g, 9, kernel=1, tile=tile)
+        outs.append(out[0])
+        sim.close()
+    for o in outs[1:]:
+        assert o[0].tobytes() == outs[0][0].tobytes()
+        assert o[1].tobytes() == outs[0][1].tobytes()
+
+
+def test_batched_uneven_equals_solo_bitwise():
+    samples = []
+    for i, (n, r) in enumerate([(32, 3.0), (96, 6.0), (64, 4.0), (160, 7.0)]):
+        geo = inputs.spheres(n, n // 2 + 3, n // 4 + 5, r, 0.6, seed=900 + i)
+        samples.append((geo.solid,))
+    g = (1e-5, 0, 0)
+    print("[case] zmarch batched vs solo", flush=True)
+    sim, outs = run_gpu(samples, 19, "f32", g, 7, kernel=1, graph_chunk=2)
+    for i, s in enumerate(samples):
+        solo, o = run_gpu([s], 19, "f32", g, 7, kernel=1)
+        assert outs[i][0].tobytes() == o[0][0].tobytes()
+        assert outs[i][1].tobytes() == o[0][1].tobytes()
+        solo.close()
+    sim.close()
+
+
+def test_channel_config1_f32_closed_form():
+    """32^3 channel with the z-march kernel against the transient closed form."""
+    from test_oracle_pins import channel_closed_form
+    solid = inputs.channel(32, 32, 32)
+    print("[case] zmarch channel", flush=True)
+    sim, out = run_gpu([(solid,)], 19, "f32", (1e-6, 0, 0), 200, kernel=1)
+    ref = channel_closed_form(30, 1e-6, 200)
+    ux = out[0][1][0][1:-1]
+    assert np.abs(ux - ref[:, None, None]).max() <= 2e-5 * ref.max()
+    sim.close()
+
+
+def test_porous_against_oracle_f32():
+    geo = inputs.spheres(64, 48, 40, 5.0, 0.7, seed=33)
+    g = (1e-5, 0, 0)
+    print("[case] zmarch porous 64x48x40", flush=True)
+    sim, out = run_gpu([(geo.solid,)], 19, "f32", g, 100, kernel=1)
+    ref = run_oracle(19, geo.solid, None, None, g, 100)
+    err = reduced_errors(out[0], ref, geo.solid)
+    print(f"[err] {err}", flush=True)
+    assert err["u_rel_l2"] <= 1e-5
+    k, m = sim.permeability(0, 0)
+    mref, kref = oracle.reduce(ref, 0, g[0])
+    assert abs(k - kref) <= 1e-5 * abs(kref)
+    sim.close()
