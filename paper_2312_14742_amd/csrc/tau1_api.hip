@@ -16,6 +16,7 @@
 #include "tau1_device.hpp"
 #include "tau1_kernels.hpp"
 #include "tau1_zmarch.hpp"
+#include "tau1_service.hpp"
 
 using namespace tau1;
 
@@ -197,7 +198,9 @@ bool zmarch_eligible(const tau1_ctx* ctx) {
 Launch step_launch(const tau1_ctx* ctx, int kernel, int tile) {
     Launch l{};
     if (kernel == 1) {
-        l.fn = pick_zmarch(ctx->lattice, ctx->precision, tile);
+        l.fn = pick_zmarch(ctx->lattice, ctx->precision,
+                           common_variant(ctx->plan.s.data(), (int)ctx->plan.s.size()),
+                           tile_hoist(tile));
         l.block = dim3(zmarch_threads(tile));
         l.grid = dim3((unsigned)zmarch_grid(ctx->args[0].ntiles, tile));
         l.shmem = 0;
@@ -370,7 +373,7 @@ tau1_status reduce_t(tau1_ctx* ctx, int s, int axis, double out[4]) {
 // Selects the z-march tile (z-segment length), rebuilds and uploads the work
 // list; cached graphs are rebuilt on the next step.
 tau1_status set_tile(tau1_ctx* ctx, int tile) {
-    std::vector<int32_t> tl = zmarch_worklist(ctx->plan.s.data(), ctx->nsamples, kTileLZ[tile]);
+    std::vector<int32_t> tl = zmarch_worklist(ctx->plan.s.data(), ctx->nsamples, tile_lz(tile));
     const int64_t items = (int64_t)tl.size() / 4;
     if (items > ctx->plan.ntiles) return TAU1_E_INVALID;
     if (!tl.empty()) {

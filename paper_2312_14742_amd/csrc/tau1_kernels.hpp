@@ -130,24 +130,6 @@ __global__ __launch_bounds__(kGatherBlock) void k_gather(StepArgs a) {
     St::store(post + 3 * st, i, uz + ghz, su);
 }
 
-// ---------------------------------------------------------------------------
-// Geometry encode (a0): pack solid bytes of rows [row0, row0 + nrows) into
-// 32-node words; one thread per word.  Rows are (y, z) pairs, row = y + ny z.
-// ---------------------------------------------------------------------------
-__global__ void k_pack_mask(const uint8_t* __restrict__ solid, uint32_t* __restrict__ mask,
-                            int nx, int words, int64_t row0, int64_t nrows) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= nrows * words) return;
-    const int64_t r = t / words;
-    const int w = (int)(t % words);
-    const uint8_t* src = solid + r * nx;
-    uint32_t bits = 0;
-    const int x0 = w * 32;
-    const int x1 = min(x0 + 32, nx);
-    for (int x = x0; x < x1; ++x) bits |= (src[x] != 0 ? 1u : 0u) << (x - x0);
-    mask[(row0 + r) * words + w] = bits;
-}
-
 // State upload: staging FP64 (drho0, u0) for nodes [i0, i0 + len) of one
 // sample into both buffers; v = u + g/2; solid nodes get exact zeros.
 template <int P>
@@ -258,39 +240,6 @@ __global__ __launch_bounds__(kReduceThreads) void k_reduce_partial(StepArgs a, i
         __syncthreads();
     }
     if (threadIdx.x < 4) partial[blockIdx.x * 4 + threadIdx.x] = sh[threadIdx.x][0];
-}
-
-// Final pass over the kReduceBlocks partials (one block, fixed tree); writes
-// out[0] = mass, out[1] = permeability (or 0 when g_axis == 0), out[2] = fluid
-// count, out[3] = non-finite count.
-__global__ __launch_bounds__(kReduceThreads) void k_reduce_final(const double* __restrict__ partial,
-                                                                 int64_t n, double g_axis,
-                                                                 double* __restrict__ out) {
-    __shared__ double sh[4][kReduceThreads];
-    double acc[4] = {0, 0, 0, 0};
-    for (int b = threadIdx.x; b < kReduceBlocks; b += kReduceThreads)
-        for (int c = 0; c < 4; ++c) acc[c] += partial[b * 4 + c];
-    for (int c = 0; c < 4; ++c) sh[c][threadIdx.x] = acc[c];
-    __syncthreads();
-    for (int w = kReduceThreads / 2; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w)
-            for (int c = 0; c < 4; ++c) sh[c][threadIdx.x] += sh[c][threadIdx.x + w];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-        const double sum_drho = sh[0][0], sum_u = sh[1][0], nf = sh[2][0];
-        out[0] = nf + sum_drho;
-        out[1] = g_axis != 0.0 ? (1.0 / 6.0) * (sum_u / (double)n) / g_axis : 0.0;
-        out[2] = nf;
-        out[3] = sh[3][0];
-    }
-}
-
-// Copy probe: 16-byte vector copy, grid-stride.
-__global__ void k_copy16(const float4* __restrict__ src, float4* __restrict__ dst, int64_t n) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x)
-        dst[i] = src[i];
 }
 
 }  // namespace tau1

@@ -1,11 +1,13 @@
 // tau1_zmarch.hpp -- z-march step kernel for gfx950 (the hot path).
 //
 // Work decomposition.  One wavefront owns G whole x-rows (G = 1, 2 or 4
-// lane groups of Lg = 64/G lanes); lane gl of a group holds PX consecutive
-// nodes x = gl*PX .. gl*PX + PX - 1 of its row, so nx = Lg * PX and the
-// periodic wrap in x is a rotation inside the lane group.  The wave marches
-// along z over a segment of planes [z0, z1), keeping the partial sums of three
-// destination planes (z-1, z, z+1) in registers.
+// lane groups of Lg = 64/G lanes).  A row is cut into C chunks of Lg*K nodes;
+// lane gl of a group holds the K consecutive nodes gl*K .. gl*K + K - 1 of
+// every chunk, so nx = C * Lg * K, each memory instruction of a group covers
+// one contiguous chunk, and the periodic wrap in x is a rotation inside the
+// lane group (plus a chunk hand-over at the group's first/last lane).  The
+// wave marches along z over a segment of planes [z0, z1), keeping the partial
+// sums of three destination planes (z-1, z, z+1) in registers.
 //
 // Per source plane the wave reads the stored (drho, v) of its own row and of
 // the rows y-1 and y+1 (those two are shared with the neighbouring waves and
@@ -44,24 +46,30 @@ namespace tau1 {
 
 constexpr int kZrWaves = 4;                 // waves per workgroup
 constexpr int kZrThreads = 64 * kZrWaves;
-constexpr int kZrMaxPX = 9;
+constexpr int kZrMaxPX = 9;  // nodes per lane (C * K)
+constexpr int kZrMaxC = 3;
 
-// Tile shapes the autotuner chooses among: z-segment length per work item.
-constexpr int kNumTiles = 4;
-constexpr int kTileLZ[kNumTiles] = {16, 32, 64, 128};
+// Tile shapes the autotuner chooses among: z-segment length per work item
+// (tile % 4) and the load schedule (tile >= 4: the three source rows of a
+// plane are loaded together; otherwise one row at a time).
+constexpr int kNumTiles = 8;
+constexpr int kTileLZ[4] = {16, 32, 64, 128};
+inline int tile_lz(int tile) { return kTileLZ[tile & 3]; }
+inline bool tile_hoist(int tile) { return tile >= 4; }
 
-// (G, PX) variants compiled into the kernel; nx = (64 / G) * PX.
+// Lane layouts (G, C, K) compiled into the kernel; nx = C * (64 / G) * K.
 struct ZrVariant {
-    int g, px;
+    int g, c, k;
 };
 constexpr int kNumVariants = 15;
 constexpr ZrVariant kVariants[kNumVariants] = {
-    {1, 1}, {1, 2}, {1, 3}, {1, 4}, {1, 5}, {1, 6}, {1, 7}, {1, 8},
-    {2, 1}, {2, 3}, {2, 5}, {2, 7}, {2, 9}, {4, 1}, {4, 3}};
+    {1, 1, 1}, {1, 1, 2}, {1, 1, 3}, {1, 1, 4}, {1, 1, 5}, {1, 2, 3}, {1, 2, 4},
+    {2, 1, 1}, {2, 1, 3}, {2, 1, 5}, {2, 1, 7}, {2, 3, 3},
+    {4, 1, 1}, {4, 1, 3}, {4, 1, 5}};
 
 inline int zr_variant_for(int nx) {
     for (int v = 0; v < kNumVariants; ++v)
-        if ((64 / kVariants[v].g) * kVariants[v].px == nx) return v;
+        if (kVariants[v].c * (64 / kVariants[v].g) * kVariants[v].k == nx) return v;
     return -1;
 }
 
@@ -104,7 +112,7 @@ __device__ __forceinline__ float lane_down(float v) {
 
 // Extended solid mask: each (y, z) row holds xwords 32-bit words whose bit b
 // is the solid flag of node x = b - 1 taken periodically (so bit 0 is x = nx-1
-// and bit nx+1 is x = 0).  A lane reads the PX + 2 bits around its nodes.
+// and bit nx+1 is x = 0).  A lane reads the K + 2 bits around each chunk.
 __device__ __forceinline__ uint32_t xmask_window(const uint32_t* __restrict__ xm, int64_t row,
                                                  int xwords, int b0) {
     const uint32_t* p = xm + row * xwords + (b0 >> 5);
@@ -112,26 +120,100 @@ __device__ __forceinline__ uint32_t xmask_window(const uint32_t* __restrict__ xm
     return (uint32_t)(((hi << 32) | lo) >> (b0 & 31));
 }
 
-template <int P, int PX>
-struct RawRow {
-    typename Storage<P>::T d[PX], vx[PX], vy[PX], vz[PX];
-};
+// ---------------------------------------------------------------------------
+// Buffer access.  Each state array and the extended mask get a raw buffer
+// resource; a row's start is the uniform (scalar) offset and a lane's chunk
+// the per-lane offset, so no per-lane address arithmetic is needed.  A lane
+// that has nothing to read or write in a chunk uses an offset beyond the
+// buffer's range: such loads return zeros and such stores are dropped by the
+// hardware range check, without touching memory.
+// ---------------------------------------------------------------------------
+using rsrc_t = __amdgpu_buffer_rsrc_t;
+constexpr int kOob = 0x7ff00000;  // voffset beyond every buffer (< 2 GiB checked on the host)
 
-// Loads PX consecutive stored values of the four state arrays starting at
-// node index i (a lane's slots) and widens them to FP32.
-template <int P, int PX>
-__device__ __forceinline__ void load_row(const typename Storage<P>::S* __restrict__ base,
-                                         int64_t stride, int64_t i, float isr, float isu,
-                                         RawRow<P, PX>& r) {
-    using St = Storage<P>;
-#pragma unroll
-    for (int j = 0; j < PX; ++j) {
-        r.d[j] = St::load(base, i + j, isr);
-        r.vx[j] = St::load(base + stride, i + j, isu);
-        r.vy[j] = St::load(base + 2 * stride, i + j, isu);
-        r.vz[j] = St::load(base + 3 * stride, i + j, isu);
-    }
+__device__ __forceinline__ rsrc_t make_rsrc(const void* p, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), 0, (int)bytes, 0x00020000);
 }
+
+// Loads B bytes (B a multiple of 2) at voff + soff into w (little endian).
+template <int B>
+__device__ __forceinline__ void buf_load_bytes(rsrc_t r, int voff, int soff, uint32_t (&w)[(B + 3) / 4]) {
+    int o = 0;
+#pragma unroll
+    for (; o + 16 <= B; o += 16) {
+        const auto v = __builtin_amdgcn_raw_buffer_load_b128(r, voff + o, soff, 0);
+        w[o / 4] = v[0]; w[o / 4 + 1] = v[1]; w[o / 4 + 2] = v[2]; w[o / 4 + 3] = v[3];
+    }
+    if constexpr (B % 16 >= 12) {
+        const auto v = __builtin_amdgcn_raw_buffer_load_b96(r, voff + o, soff, 0);
+        w[o / 4] = v[0]; w[o / 4 + 1] = v[1]; w[o / 4 + 2] = v[2];
+        o += 12;
+    } else if constexpr (B % 16 >= 8) {
+        const auto v = __builtin_amdgcn_raw_buffer_load_b64(r, voff + o, soff, 0);
+        w[o / 4] = v[0]; w[o / 4 + 1] = v[1];
+        o += 8;
+    } else if constexpr (B % 16 >= 4) {
+        w[o / 4] = __builtin_amdgcn_raw_buffer_load_b32(r, voff + o, soff, 0);
+        o += 4;
+    }
+    if constexpr (B % 4 == 2) w[o / 4] = __builtin_amdgcn_raw_buffer_load_b16(r, voff + o, soff, 0);
+}
+
+template <int B>
+__device__ __forceinline__ void buf_store_bytes(rsrc_t r, int voff, int soff,
+                                                const uint32_t (&w)[(B + 3) / 4]) {
+    int o = 0;
+#pragma unroll
+    for (; o + 16 <= B; o += 16) {
+        __attribute__((ext_vector_type(4))) unsigned v = {w[o / 4], w[o / 4 + 1], w[o / 4 + 2], w[o / 4 + 3]};
+        __builtin_amdgcn_raw_buffer_store_b128(v, r, voff + o, soff, 0);
+    }
+    if constexpr (B % 16 >= 12) {
+        __attribute__((ext_vector_type(3))) unsigned v = {w[o / 4], w[o / 4 + 1], w[o / 4 + 2]};
+        __builtin_amdgcn_raw_buffer_store_b96(v, r, voff + o, soff, 0);
+        o += 12;
+    } else if constexpr (B % 16 >= 8) {
+        __attribute__((ext_vector_type(2))) unsigned v = {w[o / 4], w[o / 4 + 1]};
+        __builtin_amdgcn_raw_buffer_store_b64(v, r, voff + o, soff, 0);
+        o += 8;
+    } else if constexpr (B % 16 >= 4) {
+        __builtin_amdgcn_raw_buffer_store_b32(w[o / 4], r, voff + o, soff, 0);
+        o += 4;
+    }
+    if constexpr (B % 4 == 2) __builtin_amdgcn_raw_buffer_store_b16((unsigned short)w[o / 4], r, voff + o, soff, 0);
+}
+
+// K stored values of one array (one lane chunk) widened to FP32.
+template <int P, int K>
+__device__ __forceinline__ void load_chunk(rsrc_t r, int voff, int soff, float (&v)[K], float isc) {
+    using St = Storage<P>;
+    using S = typename St::S;
+    constexpr int B = K * (int)sizeof(S);
+    uint32_t w[(B + 3) / 4];
+    buf_load_bytes<B>(r, voff, soff, w);
+    S tmp[K];
+    __builtin_memcpy(tmp, w, sizeof(tmp));
+#pragma unroll
+    for (int j = 0; j < K; ++j) v[j] = St::load(tmp, j, isc);
+}
+
+template <int P, int K>
+__device__ __forceinline__ void store_chunk(rsrc_t r, int voff, int soff, const float (&v)[K], float sc) {
+    using St = Storage<P>;
+    using S = typename St::S;
+    constexpr int B = K * (int)sizeof(S);
+    S tmp[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) St::store(tmp, j, v[j], sc);
+    uint32_t w[(B + 3) / 4] = {};
+    __builtin_memcpy(w, tmp, sizeof(tmp));
+    buf_store_bytes<B>(r, voff, soff, w);
+}
+
+template <int PX>
+struct RawRow {
+    float d[PX], vx[PX], vy[PX], vz[PX];
+};
 
 // Per-source quantities: the equilibrium of Eq. (3) minus its weight in a
 // direction with cu = c.v is w * (A + cu * (R3 + R45 * cu)) with
@@ -163,81 +245,109 @@ __device__ __forceinline__ float feq_m(const Src& s) {
     return __builtin_fmaf(__builtin_fmaf(s.r45, cu, s.r3), cu, s.a);
 }
 
-// acc[plane][component][slot]; plane 0,1,2 = z-1, z, z+1 relative to the
-// source plane; component 0..3 = drho, jx, jy, jz.
+// Partial sums of one destination plane: [component][slot], components drho,
+// jx, jy, jz.  Three planes (z-1, z, z+1 of the source plane) rotate roles.
 template <int PX>
-struct Acc {
-    float v[3][4][PX];
+struct Plane {
+    float v[4][PX];
+};
+
+template <int PX>
+struct Planes {
+    Plane<PX>& m;  // destination plane z - 1
+    Plane<PX>& c;  // z
+    Plane<PX>& p;  // z + 1
 };
 
 template <int CX, int CY, int CZ, int PX>
-__device__ __forceinline__ void add_to(Acc<PX>& acc, int slot, float w, float u) {
-    constexpr int p = CZ + 1;
-    acc.v[p][0][slot] = __builtin_fmaf(w, u, acc.v[p][0][slot]);
-    if constexpr (CX != 0) acc.v[p][1][slot] = __builtin_fmaf(CX * w, u, acc.v[p][1][slot]);
-    if constexpr (CY != 0) acc.v[p][2][slot] = __builtin_fmaf(CY * w, u, acc.v[p][2][slot]);
-    if constexpr (CZ != 0) acc.v[p][3][slot] = __builtin_fmaf(CZ * w, u, acc.v[p][3][slot]);
+__device__ __forceinline__ void add_to(Planes<PX>& pl, int slot, float w, float u) {
+    Plane<PX>& q = CZ < 0 ? pl.m : (CZ == 0 ? pl.c : pl.p);
+    q.v[0][slot] = __builtin_fmaf(w, u, q.v[0][slot]);
+    if constexpr (CX != 0) q.v[1][slot] = __builtin_fmaf(CX * w, u, q.v[1][slot]);
+    if constexpr (CY != 0) q.v[2][slot] = __builtin_fmaf(CY * w, u, q.v[2][slot]);
+    if constexpr (CZ != 0) q.v[3][slot] = __builtin_fmaf(CZ * w, u, q.v[3][slot]);
 }
 
-// Push the direction-k contribution of every slot of a source row whose
-// directions have c_y == CY.
-template <int Q, int K, int G, int PX>
-__device__ __forceinline__ void push_dir(Acc<PX>& acc, const Src (&s)[PX], int zmask) {
+// Push the direction-KD contribution of every slot of a source row.  Slot
+// (c, j) sends to (c, j + c_x); across a lane boundary the value rotates one
+// lane inside the group, and the group's first/last lane takes it from the
+// neighbouring chunk (the node after the last of chunk c is the first of c+1).
+template <int Q, int KD, int G, int C, int K>
+__device__ __forceinline__ void push_dir(Planes<C * K>& pl, const Src (&s)[C * K], int zmask,
+                                         bool first_lane, bool last_lane) {
     using L = Lattice<Q>;
-    constexpr int CX = L::c[K].x, CY = L::c[K].y, CZ = L::c[K].z;
-    // zmask selects which destination planes this step still needs
+    constexpr int CX = L::c[KD].x, CY = L::c[KD].y, CZ = L::c[KD].z;
     if (!((zmask >> (CZ + 1)) & 1)) return;
-    constexpr float w = (float)weight<Q>(K);
+    constexpr float w = (float)weight<Q>(KD);
+    float edge[C];
 #pragma unroll
-    for (int j = 0; j < PX; ++j) {
-        const float u = feq_m<CX, CY, CZ>(s[j]);
-        const int dst = j + CX;
-        if (dst >= 0 && dst < PX) {
-            add_to<CX, CY, CZ, PX>(acc, dst, w, u);
-        } else if (dst == PX) {
-            add_to<CX, CY, CZ, PX>(acc, 0, w, lane_up<G>(u));
-        } else {
-            add_to<CX, CY, CZ, PX>(acc, PX - 1, w, lane_down<G>(u));
+    for (int c = 0; c < C; ++c) {
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            const float u = feq_m<CX, CY, CZ>(s[c * K + j]);
+            const int dst = j + CX;
+            if (dst >= 0 && dst < K) {
+                add_to<CX, CY, CZ, C * K>(pl, c * K + dst, w, u);
+            } else if (dst == K) {
+                edge[c] = lane_up<G>(u);
+            } else {
+                edge[c] = lane_down<G>(u);
+            }
+        }
+    }
+    if constexpr (CX != 0) {
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            float v = edge[c];
+            if constexpr (C > 1) {
+                if constexpr (CX > 0) v = first_lane ? edge[(c + C - 1) % C] : v;
+                else v = last_lane ? edge[(c + 1) % C] : v;
+            }
+            add_to<CX, CY, CZ, C * K>(pl, CX > 0 ? c * K : c * K + K - 1, w, v);
         }
     }
 }
 
-template <int Q, int CYSEL, int G, int PX, int K = 1>
-__device__ __forceinline__ void push_row(Acc<PX>& acc, const Src (&s)[PX], int zmask) {
-    if constexpr (K < Q) {
-        if constexpr (Lattice<Q>::c[K].y == CYSEL) push_dir<Q, K, G, PX>(acc, s, zmask);
-        push_row<Q, CYSEL, G, PX, K + 1>(acc, s, zmask);
+template <int Q, int CYSEL, int G, int C, int K, int KD = 1>
+__device__ __forceinline__ void push_row(Planes<C * K>& pl, const Src (&s)[C * K], int zmask,
+                                         bool first_lane, bool last_lane) {
+    if constexpr (KD < Q) {
+        if constexpr (Lattice<Q>::c[KD].y == CYSEL)
+            push_dir<Q, KD, G, C, K>(pl, s, zmask, first_lane, last_lane);
+        push_row<Q, CYSEL, G, C, K, KD + 1>(pl, s, zmask, first_lane, last_lane);
     }
 }
 
 // Bounce-back sums of one fluid node (one per worker lane): every direction k
 // whose neighbour x + c_k is solid returns the node's own equilibrium in k
 // along -c_k.  win[dy+1][dz+1] holds the solid bits around the node (bit 1 =
-// the node itself).
-template <int Q, int K = 1>
-__device__ __forceinline__ void bounce_sum(const Src& s, const uint32_t (&win)[3][3], float& d,
-                                           float& jx, float& jy, float& jz) {
-    if constexpr (K < Q) {
+// the node itself).  Sums are kept per weight class and weighted at the end.
+template <int Q, int KD = 1>
+__device__ __forceinline__ void bounce_sum(const Src& s, const uint32_t (&win)[3][3],
+                                           float (&d)[3], float (&j)[3][3]) {
+    if constexpr (KD < Q) {
         using L = Lattice<Q>;
-        constexpr int CX = L::c[K].x, CY = L::c[K].y, CZ = L::c[K].z;
-        constexpr float w = (float)weight<Q>(K);
-        const bool solid = (win[CY + 1][CZ + 1] >> (1 + CX)) & 1u;
-        const float u = solid ? w * feq_m<CX, CY, CZ>(s) : 0.0f;
-        d += u;
-        if constexpr (CX != 0) jx -= CX * u;
-        if constexpr (CY != 0) jy -= CY * u;
-        if constexpr (CZ != 0) jz -= CZ * u;
-        bounce_sum<Q, K + 1>(s, win, d, jx, jy, jz);
+        constexpr int CX = L::c[KD].x, CY = L::c[KD].y, CZ = L::c[KD].z;
+        constexpr int cls = (CX != 0) + (CY != 0) + (CZ != 0) - 1;  // face, edge, corner
+        // all-ones when the neighbour x + c_k is solid
+        const uint32_t m = (uint32_t)__builtin_amdgcn_sbfe((int)win[CY + 1][CZ + 1], 1 + CX, 1);
+        const float u = __builtin_bit_cast(float, __builtin_bit_cast(uint32_t, feq_m<CX, CY, CZ>(s)) & m);
+        d[cls] += u;
+        if constexpr (CX != 0) j[cls][0] -= CX * u;
+        if constexpr (CY != 0) j[cls][1] -= CY * u;
+        if constexpr (CZ != 0) j[cls][2] -= CZ * u;
+        bounce_sum<Q, KD + 1>(s, win, d, j);
     }
 }
 
-// Solid-neighbour bits (one per slot) of a lane from its nine row windows.
-template <int Q, int PX, int K = 1>
+// Solid-neighbour bits (one per node of a chunk) from the chunk's nine row
+// windows.
+template <int Q, int KD = 1>
 __device__ __forceinline__ uint32_t neighbour_solid(const uint32_t (&win)[3][3]) {
-    if constexpr (K < Q) {
+    if constexpr (KD < Q) {
         using L = Lattice<Q>;
-        constexpr int CX = L::c[K].x, CY = L::c[K].y, CZ = L::c[K].z;
-        return (win[CY + 1][CZ + 1] >> (1 + CX)) | neighbour_solid<Q, PX, K + 1>(win);
+        constexpr int CX = L::c[KD].x, CY = L::c[KD].y, CZ = L::c[KD].z;
+        return (win[CY + 1][CZ + 1] >> (1 + CX)) | neighbour_solid<Q, KD + 1>(win);
     } else {
         return 0u;
     }
@@ -253,7 +363,7 @@ __device__ __forceinline__ int nth_set_bit(uint64_t m, int n) {
     int pos = 0;
 #pragma unroll
     for (int width = 32; width >= 1; width >>= 1) {
-        const uint64_t part = (m >> pos) & ((width == 64 ? ~0ull : ((1ull << width) - 1)));
+        const uint64_t part = (m >> pos) & ((1ull << width) - 1);
         const int c = __builtin_popcountll(part);
         if (n >= c) {
             n -= c;
@@ -263,216 +373,354 @@ __device__ __forceinline__ int nth_set_bit(uint64_t m, int n) {
     return pos;
 }
 
-// One work item: G rows starting at row-group rg, destination planes [z0, z1).
-template <int Q, int P, int G, int PX>
-__device__ __forceinline__ void zr_item(const StepArgs& a, const SampleDev& sd, int rg, int z0,
-                                        int z1, float* __restrict__ lds) {
-    using St = Storage<P>;
-    using S = typename St::S;
+__device__ __forceinline__ int64_t uniform64(int64_t v) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)((uint64_t)v >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+// Constants of one work item (one wave).
+template <int P, int G, int C, int K>
+struct ZrItem {
+    static constexpr int Lg = 64 / G;
+    static constexpr int PX = C * K;
+    static constexpr int ES = (int)sizeof(typename Storage<P>::S);
+    rsrc_t pre[4], post[4], xm;
+    int lane, gl;
+    bool first_lane, last_lane, active;
+    int nx, ny, nz, xw, z0, z1;
+    int yc, ym, yp;
+    int voff[C];   // byte offset of the lane's chunk c inside a row
+    int woff[C];   // byte offset of the lane's mask window word, chunk c
+    float isr, isu, sr, su, gx, gy, gz;
+    float* lds_state;
+    uint32_t* lds_win;
+};
+
+// Nine row windows (rows y-1..y+1 x planes z-1..z+1) around plane zc.
+template <int P, int G, int C, int K>
+__device__ __forceinline__ void load_windows(const ZrItem<P, G, C, K>& it, int zc,
+                                             uint32_t (&win)[C][3][3]) {
+    const int zrow[3] = {wrapi(zc - 1, it.nz), zc, wrapi(zc + 1, it.nz)};
+    const int yrow[3] = {it.ym, it.yc, it.yp};
+#pragma unroll
+    for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+        for (int dz = 0; dz < 3; ++dz) {
+            const int roff = (zrow[dz] * it.ny + yrow[dy]) * it.xw * 4;
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                const auto v = G == 1 ? __builtin_amdgcn_raw_buffer_load_b64(it.xm, it.woff[c], roff, 0)
+                                      : __builtin_amdgcn_raw_buffer_load_b64(it.xm, it.woff[c] + roff, 0, 0);
+                const uint64_t u = ((uint64_t)v[1] << 32) | v[0];
+                win[c][dy][dz] = (uint32_t)(u >> ((c * (64 / G) * K + it.gl * K) & 31));
+            }
+        }
+}
+
+template <int C, int K>
+__device__ __forceinline__ uint32_t fluid_bits(const uint32_t (&win)[C][3][3], int dy) {
+    constexpr uint32_t mK = (1u << K) - 1u;
+    uint32_t f = 0;
+#pragma unroll
+    for (int c = 0; c < C; ++c) f |= (~(win[c][dy][1] >> 1) & mK) << (c * K);
+    return f;
+}
+
+// One source row's state (C chunks of K nodes), chunks without fluid read as
+// zeros at no memory cost.
+template <int P, int G, int C, int K>
+__device__ __forceinline__ void load_row(const ZrItem<P, G, C, K>& it, int row, uint32_t fl,
+                                         RawRow<C * K>& r) {
+    constexpr uint32_t mK = (1u << K) - 1u;
+    const int roff = row * it.nx * ZrItem<P, G, C, K>::ES;
+    const int soff = G == 1 ? roff : 0;
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        const int vo = ((fl >> (c * K)) & mK) ? it.voff[c] + (G == 1 ? 0 : roff) : kOob;
+        float t0[K], t1[K], t2[K], t3[K];
+        load_chunk<P, K>(it.pre[0], vo, soff, t0, it.isr);
+        load_chunk<P, K>(it.pre[1], vo, soff, t1, it.isu);
+        load_chunk<P, K>(it.pre[2], vo, soff, t2, it.isu);
+        load_chunk<P, K>(it.pre[3], vo, soff, t3, it.isu);
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            r.d[c * K + j] = t0[j];
+            r.vx[c * K + j] = t1[j];
+            r.vy[c * K + j] = t2[j];
+            r.vz[c * K + j] = t3[j];
+        }
+    }
+}
+
+template <int Q, int P, int G, int C, int K>
+__device__ __forceinline__ void bounce_back(const ZrItem<P, G, C, K>& it, Plane<C * K>& pc,
+                                            const uint32_t (&win)[C][3][3], uint32_t fown,
+                                            const RawRow<C * K>& ro) {
+    constexpr int PX = C * K;
     constexpr int Lg = 64 / G;
-    constexpr uint32_t mPX = (1u << PX) - 1u;
-    const int lane = __lane_id();
-    const int grp = lane / Lg;
-    const int gl = lane % Lg;
-    const int nx = sd.nx, ny = sd.ny, nz = sd.nz;
-    const int y = rg * G + grp;
-    const bool active = y < ny;
-    const int yc = active ? y : ny - 1;
-    const int ym = wrapi(yc - 1, ny), yp = wrapi(yc + 1, ny);
-    const int x0 = gl * PX;
-    const int64_t stride = sd.stride;
-    const S* pre = reinterpret_cast<const S*>(a.base + sd.state[a.parity]);
-    S* post = reinterpret_cast<S*>(a.base + sd.state[a.parity ^ 1]);
-    const uint32_t* xm = reinterpret_cast<const uint32_t*>(a.base + sd.xmask);
-    const int xw = sd.xwords;
-    const float isr = inv_scale_rho<P>(a), isu = inv_scale_u<P>(a);
-    const float sr = scale_rho<P>(a), su = scale_u<P>(a);
-    const float gx = 2.0f * a.ghf[0], gy = 2.0f * a.ghf[1], gz = 2.0f * a.ghf[2];
-
-    Acc<PX> acc;
+    uint32_t nb = 0;
 #pragma unroll
-    for (int p = 0; p < 3; ++p)
+    for (int c = 0; c < C; ++c) nb |= (neighbour_solid<Q>(win[c]) & ((1u << K) - 1u)) << (c * K);
+    const uint32_t bmask = it.active ? (fown & nb) : 0u;
+    uint64_t bal[PX];
+    int total = 0;
 #pragma unroll
-        for (int c = 0; c < 4; ++c)
+    for (int j = 0; j < PX; ++j) {
+        bal[j] = __ballot((bmask >> j) & 1u);
+        total += __builtin_popcountll(bal[j]);
+    }
+    if (!total) return;
+    const int lane = it.lane;
+    if (bmask) {
 #pragma unroll
-            for (int j = 0; j < PX; ++j) acc.v[p][c][j] = 0.0f;
+        for (int j = 0; j < PX; ++j) {
+            it.lds_state[(0 * PX + j) * 64 + lane] = ro.d[j];
+            it.lds_state[(1 * PX + j) * 64 + lane] = ro.vx[j];
+            it.lds_state[(2 * PX + j) * 64 + lane] = ro.vy[j];
+            it.lds_state[(3 * PX + j) * 64 + lane] = ro.vz[j];
+        }
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+#pragma unroll
+            for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+                for (int dz = 0; dz < 3; ++dz)
+                    it.lds_win[((c * 3 + dy) * 3 + dz) * 64 + lane] = win[c][dy][dz];
+    }
+    __builtin_amdgcn_wave_barrier();
+    for (int base = 0; base < total; base += 64) {
+        const int i = base + lane;
+        if (i < total) {
+            // entry i in slot-major order -> (slot, owner lane)
+            int slot = 0, rank = i, cum = 0;
+            uint64_t m = bal[0];
+#pragma unroll
+            for (int j = 0; j < PX; ++j) {
+                const int cnt = __builtin_popcountll(bal[j]);
+                if (i >= cum && i < cum + cnt) {
+                    slot = j;
+                    rank = i - cum;
+                    m = bal[j];
+                }
+                cum += cnt;
+            }
+            const int owner = nth_set_bit(m, rank);
+            const int ch = slot / K, jj = slot - (slot / K) * K;
+            uint32_t w2[3][3];
+#pragma unroll
+            for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+                for (int dz = 0; dz < 3; ++dz)
+                    w2[dy][dz] = it.lds_win[((ch * 3 + dy) * 3 + dz) * 64 + owner] >> jj;
+            float* e = it.lds_state + slot * 64 + owner;
+            const Src sw = make_src(e[0], e[PX * 64], e[2 * PX * 64], e[3 * PX * 64]);
+            float d[3] = {0.f, 0.f, 0.f};
+            float jv[3][3] = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};
+            bounce_sum<Q>(sw, w2, d, jv);
+            constexpr float wf = (float)Lattice<Q>::w_face, we = (float)Lattice<Q>::w_edge,
+                            wc = (float)Lattice<Q>::w_corner;
+            e[0] = wf * d[0] + we * d[1] + wc * d[2];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) e[(1 + a) * PX * 64] = wf * jv[0][a] + we * jv[1][a] + wc * jv[2][a];
+        }
+    }
+    __builtin_amdgcn_wave_barrier();
+    if (bmask) {
+#pragma unroll
+        for (int j = 0; j < PX; ++j) {
+            if ((bmask >> j) & 1u) {
+#pragma unroll
+                for (int c = 0; c < 4; ++c) pc.v[c][j] += it.lds_state[(c * PX + j) * 64 + lane];
+            }
+        }
+    }
+    __builtin_amdgcn_wave_barrier();
+}
 
-    uint32_t fluid_prev = 0;  // own-row fluid bits of plane zs - 1
-
-    for (int zs = z0 - 1; zs <= z1; ++zs) {
-        // destination planes zs-1, zs, zs+1 that belong to this segment
-        const int zmask = ((zs - 1 >= z0 && zs - 1 < z1) ? 1 : 0) |
-                          ((zs >= z0 && zs < z1) ? 2 : 0) |
-                          ((zs + 1 >= z0 && zs + 1 < z1) ? 4 : 0);
-        const int zc = wrapi(zs % nz, nz);
-        const int zm = wrapi(zc - 1, nz), zp = wrapi(zc + 1, nz);
-        const int yrow[3] = {ym, yc, yp};
-        const int zrow[3] = {zm, zc, zp};
-        uint32_t win[3][3];
+// One source plane zs: pl.m, pl.c, pl.p are the destination planes zs-1, zs,
+// zs+1 (pl.p zero on entry).  Finalises and stores plane zs-1 at the end.
+template <int Q, int P, int G, int C, int K, bool HOIST>
+__device__ __forceinline__ void zr_step(const ZrItem<P, G, C, K>& it, int zs, Planes<C * K> pl,
+                                        uint32_t (&win_next)[C][3][3], uint32_t& fluid_prev) {
+    constexpr int PX = C * K;
+    constexpr int Lg = 64 / G;
+    constexpr uint32_t mK = (1u << K) - 1u;
+    const int z0 = it.z0, z1 = it.z1, ny = it.ny, nz = it.nz;
+    const int zmask = ((zs - 1 >= z0 && zs - 1 < z1) ? 1 : 0) |
+                      ((zs >= z0 && zs < z1) ? 2 : 0) |
+                      ((zs + 1 >= z0 && zs + 1 < z1) ? 4 : 0);
+    const int zc = wrapi(zs % nz, nz);
+    uint32_t win[C][3][3];
+#pragma unroll
+    for (int c = 0; c < C; ++c)
 #pragma unroll
         for (int dy = 0; dy < 3; ++dy)
 #pragma unroll
-            for (int dz = 0; dz < 3; ++dz)
-                win[dy][dz] = xmask_window(xm, (int64_t)zrow[dz] * ny + yrow[dy], xw, x0);
+            for (int dz = 0; dz < 3; ++dz) win[c][dy][dz] = win_next[c][dy][dz];
 
-        // ---- neighbour rows y-1 (their c_y = +1 directions) and y+1 (c_y = -1)
-#pragma unroll
-        for (int side = 0; side < 2; ++side) {
-            const int yr = side == 0 ? ym : yp;
-            const uint32_t fl = ~(win[side == 0 ? 0 : 2][1] >> 1) & mPX;
-            RawRow<P, PX> raw;
-            if (fl) {
-                load_row<P, PX>(pre, stride, ((int64_t)zc * ny + yr) * nx + x0, isr, isu, raw);
-            } else {
-#pragma unroll
-                for (int j = 0; j < PX; ++j) raw.d[j] = raw.vx[j] = raw.vy[j] = raw.vz[j] = 0.0f;
-            }
-            Src s[PX];
-#pragma unroll
-            for (int j = 0; j < PX; ++j) s[j] = make_src(raw.d[j], raw.vx[j], raw.vy[j], raw.vz[j]);
-            if (side == 0)
-                push_row<Q, 1, G, PX>(acc, s, zmask);
-            else
-                push_row<Q, -1, G, PX>(acc, s, zmask);
-        }
+    const uint32_t flm = fluid_bits<C, K>(win, 0);
+    const uint32_t flp = fluid_bits<C, K>(win, 2);
+    const uint32_t fown = fluid_bits<C, K>(win, 1);
+    const int rm_ = zc * ny + it.ym, rp_ = zc * ny + it.yp, ro_ = zc * ny + it.yc;
+    RawRow<PX> rm, rp, ro;
+    if constexpr (HOIST) {
+        load_row(it, rm_, flm, rm);
+        load_row(it, rp_, flp, rp);
+        load_row(it, ro_, fown, ro);
+    }
+    if (zs < z1) load_windows(it, wrapi((zs + 1) % nz, nz), win_next);
 
-        // ---- own row: c_y = 0 directions, rest, bounce-back
-        const uint32_t fown = ~(win[1][1] >> 1) & mPX;
-        RawRow<P, PX> raw;
-        if (fown) {
-            load_row<P, PX>(pre, stride, ((int64_t)zc * ny + yc) * nx + x0, isr, isu, raw);
-        } else {
+    // ---- neighbour rows: y-1 sends its c_y = +1 directions, y+1 its c_y = -1
+    {
+        if constexpr (!HOIST) load_row(it, rm_, flm, rm);
+        Src s[PX];
 #pragma unroll
-            for (int j = 0; j < PX; ++j) raw.d[j] = raw.vx[j] = raw.vy[j] = raw.vz[j] = 0.0f;
-        }
-        {
-            Src s[PX];
+        for (int j = 0; j < PX; ++j) s[j] = make_src(rm.d[j], rm.vx[j], rm.vy[j], rm.vz[j]);
+        push_row<Q, 1, G, C, K>(pl, s, zmask, it.first_lane, it.last_lane);
+    }
+    {
+        if constexpr (!HOIST) load_row(it, rp_, flp, rp);
+        Src s[PX];
 #pragma unroll
-            for (int j = 0; j < PX; ++j) s[j] = make_src(raw.d[j], raw.vx[j], raw.vy[j], raw.vz[j]);
-            push_row<Q, 0, G, PX>(acc, s, zmask);
-            if (zmask & 2) {
-                constexpr float w0 = (float)weight<Q>(0);
+        for (int j = 0; j < PX; ++j) s[j] = make_src(rp.d[j], rp.vx[j], rp.vy[j], rp.vz[j]);
+        push_row<Q, -1, G, C, K>(pl, s, zmask, it.first_lane, it.last_lane);
+    }
+    if constexpr (!HOIST) load_row(it, ro_, fown, ro);
+    // ---- own row: c_y = 0 directions and the rest population
+    {
+        Src s[PX];
 #pragma unroll
-                for (int j = 0; j < PX; ++j) acc.v[1][0][j] = __builtin_fmaf(w0, s[j].a, acc.v[1][0][j]);
-            }
-        }
-
+        for (int j = 0; j < PX; ++j) s[j] = make_src(ro.d[j], ro.vx[j], ro.vy[j], ro.vz[j]);
+        push_row<Q, 0, G, C, K>(pl, s, zmask, it.first_lane, it.last_lane);
         if (zmask & 2) {
-            // fluid nodes of this row with at least one solid neighbour
-            const uint32_t bmask =
-                active ? (fown & neighbour_solid<Q, PX>(win) & mPX) : 0u;
-            uint64_t bal[PX];
-            int total = 0;
+            constexpr float w0 = (float)weight<Q>(0);
 #pragma unroll
-            for (int j = 0; j < PX; ++j) {
-                bal[j] = __ballot((bmask >> j) & 1u);
-                total += __builtin_popcountll(bal[j]);
-            }
-            if (total) {
-                // dense copy of the wave's own-row state: lds[c][slot][lane]
-                if (bmask) {
-#pragma unroll
-                    for (int j = 0; j < PX; ++j) {
-                        lds[(0 * PX + j) * 64 + lane] = raw.d[j];
-                        lds[(1 * PX + j) * 64 + lane] = raw.vx[j];
-                        lds[(2 * PX + j) * 64 + lane] = raw.vy[j];
-                        lds[(3 * PX + j) * 64 + lane] = raw.vz[j];
-                    }
-                }
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                __builtin_amdgcn_wave_barrier();
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-                for (int base = 0; base < total; base += 64) {
-                    const int i = base + lane;
-                    if (i < total) {
-                        // entry i in slot-major order -> (slot, owner lane)
-                        int slot = 0, rank = i, cum = 0;
-                        uint64_t m = bal[0];
-#pragma unroll
-                        for (int j = 0; j < PX; ++j) {
-                            const int c = __builtin_popcountll(bal[j]);
-                            if (i >= cum && i < cum + c) {
-                                slot = j;
-                                rank = i - cum;
-                                m = bal[j];
-                            }
-                            cum += c;
-                        }
-                        const int owner = nth_set_bit(m, rank);
-                        const int oy = rg * G + owner / Lg;
-                        const int ox = (owner % Lg) * PX + slot;
-                        const int oym = wrapi(oy - 1, ny), oyp = wrapi(oy + 1, ny);
-                        const int oyrow[3] = {oym, oy, oyp};
-                        uint32_t w2[3][3];
-#pragma unroll
-                        for (int dy = 0; dy < 3; ++dy)
-#pragma unroll
-                            for (int dz = 0; dz < 3; ++dz)
-                                w2[dy][dz] = xmask_window(xm, (int64_t)zrow[dz] * ny + oyrow[dy], xw, ox);
-                        float* e = lds + slot * 64 + owner;
-                        const Src s = make_src(e[0], e[PX * 64], e[2 * PX * 64], e[3 * PX * 64]);
-                        float d = 0.f, jx = 0.f, jy = 0.f, jz = 0.f;
-                        bounce_sum<Q>(s, w2, d, jx, jy, jz);
-                        e[0] = d;
-                        e[PX * 64] = jx;
-                        e[2 * PX * 64] = jy;
-                        e[3 * PX * 64] = jz;
-                    }
-                }
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                __builtin_amdgcn_wave_barrier();
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-                if (bmask) {
-#pragma unroll
-                    for (int j = 0; j < PX; ++j) {
-                        if ((bmask >> j) & 1u) {
-#pragma unroll
-                            for (int c = 0; c < 4; ++c)
-                                acc.v[1][c][j] += lds[(c * PX + j) * 64 + lane];
-                        }
-                    }
-                }
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                __builtin_amdgcn_wave_barrier();
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            }
+            for (int j = 0; j < PX; ++j) pl.c.v[0][j] = __builtin_fmaf(w0, s[j].a, pl.c.v[0][j]);
         }
+    }
+    // ---- halfway bounce-back of this plane's wall nodes, compacted per wave
+    if (zmask & 2) bounce_back<Q, P, G, C, K>(it, pl.c, win, fown, ro);
 
-        // ---- plane zs - 1 is complete: finalise and store (fluid slots only)
-        if ((zmask & 1) && active && fluid_prev) {
-            const int zo = wrapi(zc - 1, nz);
-            const int64_t i0 = ((int64_t)zo * ny + yc) * nx + x0;
+    // ---- plane zs - 1 is complete: finalise and store whole chunks (solid
+    // slots rewrite their zeros); chunks without fluid are dropped
+    if ((zmask & 1) && it.active) {
+        const int ro2 = (wrapi(zc - 1, nz) * ny + it.yc) * it.nx * ZrItem<P, G, C, K>::ES;
+        const int so = G == 1 ? ro2 : 0;
 #pragma unroll
-            for (int j = 0; j < PX; ++j) {
-                if ((fluid_prev >> j) & 1u) {
-                    const float d = acc.v[0][0][j];
-                    const float r = __builtin_amdgcn_rcpf(1.0f + d);
-                    St::store(post, i0 + j, d, sr);
-                    St::store(post + stride, i0 + j, __builtin_fmaf(acc.v[0][1][j], r, gx), su);
-                    St::store(post + 2 * stride, i0 + j, __builtin_fmaf(acc.v[0][2][j], r, gy), su);
-                    St::store(post + 3 * stride, i0 + j, __builtin_fmaf(acc.v[0][3][j], r, gz), su);
-                }
+        for (int c = 0; c < C; ++c) {
+            float od[K], ox[K], oy[K], oz[K];
+#pragma unroll
+            for (int j = 0; j < K; ++j) {
+                const int sl = c * K + j;
+                const bool f = (fluid_prev >> sl) & 1u;
+                const float d = pl.m.v[0][sl];
+                const float r = __builtin_amdgcn_rcpf(1.0f + d);
+                od[j] = f ? d : 0.0f;
+                ox[j] = f ? __builtin_fmaf(pl.m.v[1][sl], r, it.gx) : 0.0f;
+                oy[j] = f ? __builtin_fmaf(pl.m.v[2][sl], r, it.gy) : 0.0f;
+                oz[j] = f ? __builtin_fmaf(pl.m.v[3][sl], r, it.gz) : 0.0f;
             }
+            const int vo = ((fluid_prev >> (c * K)) & mK) ? it.voff[c] + (G == 1 ? 0 : ro2) : kOob;
+            store_chunk<P, K>(it.post[0], vo, so, od, it.sr);
+            store_chunk<P, K>(it.post[1], vo, so, ox, it.su);
+            store_chunk<P, K>(it.post[2], vo, so, oy, it.su);
+            store_chunk<P, K>(it.post[3], vo, so, oz, it.su);
         }
-        fluid_prev = fown;
-        // rotate the destination planes
+    }
+    fluid_prev = fown;
+}
+
+template <int PX>
+__device__ __forceinline__ void zero_plane(Plane<PX>& q) {
 #pragma unroll
-        for (int c = 0; c < 4; ++c)
+    for (int c = 0; c < 4; ++c)
 #pragma unroll
-            for (int j = 0; j < PX; ++j) {
-                acc.v[0][c][j] = acc.v[1][c][j];
-                acc.v[1][c][j] = acc.v[2][c][j];
-                acc.v[2][c][j] = 0.0f;
-            }
+        for (int j = 0; j < PX; ++j) q.v[c][j] = 0.0f;
+}
+
+// One work item: G rows starting at row-group rg, destination planes [z0, z1).
+// The three destination planes rotate roles statically (the march is
+// unrolled by three), so no partial sums are copied between planes.
+// The sample descriptor is read field by field with its own types and every
+// value is marked wave-uniform, so per-item quantities live in scalar registers.
+template <int Q, int P, int G, int C, int K, bool HOIST>
+__device__ __forceinline__ void zr_item(const StepArgs& a, const SampleDev* sd, int rg, int z0,
+                                        int z1, float* __restrict__ lds) {
+    using St = Storage<P>;
+    using S = typename St::S;
+    using It = ZrItem<P, G, C, K>;
+    constexpr int PX = C * K;
+    It it;
+    it.lane = __lane_id();
+    // with one row per wave the row is uniform; with G rows it depends on the lane group
+    const int grp = G == 1 ? 0 : it.lane / It::Lg;
+    it.gl = G == 1 ? it.lane : it.lane % It::Lg;
+    it.first_lane = it.gl == 0;
+    it.last_lane = it.gl == It::Lg - 1;
+    it.nx = __builtin_amdgcn_readfirstlane(sd->nx);
+    it.ny = __builtin_amdgcn_readfirstlane(sd->ny);
+    it.nz = __builtin_amdgcn_readfirstlane(sd->nz);
+    it.xw = __builtin_amdgcn_readfirstlane(sd->xwords);
+    it.z0 = z0; it.z1 = z1;
+    const int y = rg * G + grp;
+    it.active = y < it.ny;
+    it.yc = it.active ? y : it.ny - 1;
+    it.ym = wrapi(it.yc - 1, it.ny);
+    it.yp = wrapi(it.yc + 1, it.ny);
+    const int64_t stride = uniform64(sd->stride);
+    const uint32_t abytes = (uint32_t)(stride * It::ES);
+    const int64_t st0 = uniform64(sd->state[0]), st1 = uniform64(sd->state[1]);
+    const S* pre = reinterpret_cast<const S*>(a.base + (a.parity ? st1 : st0));
+    S* post = reinterpret_cast<S*>(a.base + (a.parity ? st0 : st1));
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        it.pre[c] = make_rsrc(pre + c * stride, abytes);
+        it.post[c] = make_rsrc(post + c * stride, abytes);
+    }
+    it.xm = make_rsrc(a.base + uniform64(sd->xmask),
+                      (uint32_t)(((int64_t)it.xw * it.ny * it.nz + 2) * 4));
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        const int x0 = c * (It::Lg * K) + it.gl * K;
+        it.voff[c] = x0 * It::ES;
+        it.woff[c] = (x0 >> 5) * 4;
+    }
+    it.isr = inv_scale_rho<P>(a); it.isu = inv_scale_u<P>(a);
+    it.sr = scale_rho<P>(a); it.su = scale_u<P>(a);
+    it.gx = 2.0f * a.ghf[0]; it.gy = 2.0f * a.ghf[1]; it.gz = 2.0f * a.ghf[2];
+    it.lds_state = lds;
+    it.lds_win = reinterpret_cast<uint32_t*>(lds + 4 * PX * 64);
+
+    Plane<PX> A, B, Cp;
+    zero_plane(A);
+    zero_plane(B);
+    zero_plane(Cp);
+    uint32_t fluid_prev = 0;
+    uint32_t win_next[C][3][3];
+    load_windows(it, wrapi((z0 - 1) % it.nz, it.nz), win_next);
+    int zs = z0 - 1;
+    while (true) {
+        zr_step<Q, P, G, C, K, HOIST>(it, zs, Planes<PX>{A, B, Cp}, win_next, fluid_prev);
+        zero_plane(A);
+        if (++zs > z1) break;
+        zr_step<Q, P, G, C, K, HOIST>(it, zs, Planes<PX>{B, Cp, A}, win_next, fluid_prev);
+        zero_plane(B);
+        if (++zs > z1) break;
+        zr_step<Q, P, G, C, K, HOIST>(it, zs, Planes<PX>{Cp, A, B}, win_next, fluid_prev);
+        zero_plane(Cp);
+        if (++zs > z1) break;
     }
 }
 
 // Work item (4 x int32): sample, row group, z-segment start, z-segment end.
 // Workgroups are remapped so that each XCD walks a contiguous range of items
-// (neighbouring rows share their y-1 / y+1 reads in that XCD's L2).
-template <int Q, int P>
+// (neighbouring rows share their y-1 / y+1 reads in that XCD's L2).  V >= 0
+// compiles one lane layout only (its register budget alone sets occupancy);
+// V = -1 switches per item, for batches of differently sized samples.
+template <int Q, int P, int V, bool HOIST>
 __global__ __launch_bounds__(kZrThreads) void k_zmarch(StepArgs a) {
-    __shared__ float lds_all[kZrWaves][4 * kZrMaxPX * 64];
+    __shared__ float lds_all[kZrWaves][(4 * kZrMaxPX + 9 * kZrMaxC) * 64];
     const int wave = threadIdx.x >> 6;
     const int nwg = gridDim.x;
     const int b = blockIdx.x;
@@ -481,55 +729,48 @@ __global__ __launch_bounds__(kZrThreads) void k_zmarch(StepArgs a) {
     const int xcd = b % 8, k = b / 8;
     const int lb = xcd * per + k;
     const int nwaves = ((nwg + 7) / 8) * 8 * kZrWaves;
-    for (int item = lb * kZrWaves + wave; item < a.ntiles; item += nwaves) {
-        const int4 t = reinterpret_cast<const int4*>(a.tiles)[item];
-        const SampleDev& sd = a.samples[t.x];
+    // the item index is uniform across the wave; say so, so that every
+    // per-item quantity (sample descriptor, buffer resources) stays scalar
+    const int first = __builtin_amdgcn_readfirstlane(lb * kZrWaves + wave);
+    for (int item = first; item < a.ntiles; item += nwaves) {
+        const int4 tv = reinterpret_cast<const int4*>(a.tiles)[item];
+        const int4 t = make_int4(__builtin_amdgcn_readfirstlane(tv.x), __builtin_amdgcn_readfirstlane(tv.y),
+                                 __builtin_amdgcn_readfirstlane(tv.z), __builtin_amdgcn_readfirstlane(tv.w));
+        const SampleDev* sd = a.samples + t.x;
         float* lds = lds_all[wave];
-        switch (sd.variant) {
-#define TAU1_ZR_CASE(V, GG, PP)                                      \
-    case V:                                                          \
-        zr_item<Q, P, GG, PP>(a, sd, t.y, t.z, t.w, lds);            \
-        break;
-            TAU1_ZR_CASE(0, 1, 1)
-            TAU1_ZR_CASE(1, 1, 2)
-            TAU1_ZR_CASE(2, 1, 3)
-            TAU1_ZR_CASE(3, 1, 4)
-            TAU1_ZR_CASE(4, 1, 5)
-            TAU1_ZR_CASE(5, 1, 6)
-            TAU1_ZR_CASE(6, 1, 7)
-            TAU1_ZR_CASE(7, 1, 8)
-            TAU1_ZR_CASE(8, 2, 1)
-            TAU1_ZR_CASE(9, 2, 3)
-            TAU1_ZR_CASE(10, 2, 5)
-            TAU1_ZR_CASE(11, 2, 7)
-            TAU1_ZR_CASE(12, 2, 9)
-            TAU1_ZR_CASE(13, 4, 1)
-            TAU1_ZR_CASE(14, 4, 3)
+#define TAU1_ZR_CASE(VV, GG, CC, KK)                                          \
+    if constexpr (V == VV || V < 0) {                                         \
+        if (V >= 0 || __builtin_amdgcn_readfirstlane(sd->variant) == VV) {    \
+            zr_item<Q, P, GG, CC, KK, HOIST>(a, sd, t.y, t.z, t.w, lds);     \
+            continue;                                                         \
+        }                                                                     \
+    }
+        TAU1_ZR_CASE(0, 1, 1, 1)
+        TAU1_ZR_CASE(1, 1, 1, 2)
+        TAU1_ZR_CASE(2, 1, 1, 3)
+        TAU1_ZR_CASE(3, 1, 1, 4)
+        TAU1_ZR_CASE(4, 1, 1, 5)
+        TAU1_ZR_CASE(5, 1, 2, 3)
+        TAU1_ZR_CASE(6, 1, 2, 4)
+        TAU1_ZR_CASE(7, 2, 1, 1)
+        TAU1_ZR_CASE(8, 2, 1, 3)
+        TAU1_ZR_CASE(9, 2, 1, 5)
+        TAU1_ZR_CASE(10, 2, 1, 7)
+        TAU1_ZR_CASE(11, 2, 3, 3)
+        TAU1_ZR_CASE(12, 4, 1, 1)
+        TAU1_ZR_CASE(13, 4, 1, 3)
+        TAU1_ZR_CASE(14, 4, 1, 5)
 #undef TAU1_ZR_CASE
-            default:
-                break;
-        }
     }
 }
 
-// Extended-mask builder: row words of the periodic, one-bit-shifted mask.
-__global__ void k_build_xmask(const uint32_t* __restrict__ mask, uint32_t* __restrict__ xm,
-                              int nx, int words, int xwords, int64_t nrows) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= nrows * xwords) return;
-    const int64_t r = t / xwords;
-    const int w = (int)(t % xwords);
-    const uint32_t* row = mask + r * words;
-    uint32_t out = 0;
-    for (int b = 0; b < 32; ++b) {
-        const int e = w * 32 + b;  // extended bit e <-> x = e - 1 (periodic)
-        if (e > nx + 1) break;
-        int x = e - 1;
-        x = x < 0 ? x + nx : (x >= nx ? x - nx : x);
-        out |= ((row[x >> 5] >> (x & 31)) & 1u) << b;
-    }
-    xm[t] = out;
-}
+// Kernel table of one (lattice, precision) pair; defined in the per-pair
+// translation units built from tau1_zmarch_inst.hip.
+#define TAU1_ZM_TABLE_DECL(QQ, PP) void* zm_kernel_##QQ##_##PP(int variant, bool hoist);
+TAU1_ZM_TABLE_DECL(15, 1) TAU1_ZM_TABLE_DECL(15, 2) TAU1_ZM_TABLE_DECL(15, 3)
+TAU1_ZM_TABLE_DECL(19, 1) TAU1_ZM_TABLE_DECL(19, 2) TAU1_ZM_TABLE_DECL(19, 3)
+TAU1_ZM_TABLE_DECL(27, 1) TAU1_ZM_TABLE_DECL(27, 2) TAU1_ZM_TABLE_DECL(27, 3)
+#undef TAU1_ZM_TABLE_DECL
 
 // ---------------------------------------------------------------------------
 // Host helpers
@@ -544,22 +785,28 @@ inline bool zmarch_tile_ok(int, int prec, int tile) {
 
 inline int zmarch_default_tile(int, int) { return 2; }  // z-segments of 64 planes
 
-template <int Q, int P>
-void* zmarch_fn() { return reinterpret_cast<void*>(&k_zmarch<Q, P>); }
-
-inline void* pick_zmarch(int q, int p, int) {
+inline void* pick_zmarch(int q, int p, int variant, bool hoist) {
     switch (q * 10 + p) {
-        case 151: return zmarch_fn<15, kF32>();
-        case 152: return zmarch_fn<15, kF16>();
-        case 153: return zmarch_fn<15, kBF16>();
-        case 191: return zmarch_fn<19, kF32>();
-        case 192: return zmarch_fn<19, kF16>();
-        case 193: return zmarch_fn<19, kBF16>();
-        case 271: return zmarch_fn<27, kF32>();
-        case 272: return zmarch_fn<27, kF16>();
-        case 273: return zmarch_fn<27, kBF16>();
+        case 151: return zm_kernel_15_1(variant, hoist);
+        case 152: return zm_kernel_15_2(variant, hoist);
+        case 153: return zm_kernel_15_3(variant, hoist);
+        case 191: return zm_kernel_19_1(variant, hoist);
+        case 192: return zm_kernel_19_2(variant, hoist);
+        case 193: return zm_kernel_19_3(variant, hoist);
+        case 271: return zm_kernel_27_1(variant, hoist);
+        case 272: return zm_kernel_27_2(variant, hoist);
+        case 273: return zm_kernel_27_3(variant, hoist);
     }
     return nullptr;
+}
+
+// Lane layout shared by every sample of a context, or -1 when they differ.
+template <typename SH>
+inline int common_variant(const SH* s, int n) {
+    int v = n > 0 ? s[0].dev.variant : -1;
+    for (int i = 1; i < n; ++i)
+        if (s[i].dev.variant != v) return -1;
+    return v;
 }
 
 inline int zmarch_threads(int) { return kZrThreads; }
@@ -573,11 +820,18 @@ inline int64_t zmarch_grid(int64_t nitems, int) {
     return (g + 7) / 8 * 8;
 }
 
+// Supported when every sample has a lane layout and each state array and
+// mask fits the 32-bit buffer offsets below the out-of-range offset.
 template <typename SH>
 inline bool zmarch_supported(int, int prec, const SH* s, int n) {
     if (!zmarch_precision_ok(prec)) return false;
-    for (int i = 0; i < n; ++i)
-        if (s[i].dev.variant < 0) return false;
+    const int64_t es = storage_bytes(prec);
+    for (int i = 0; i < n; ++i) {
+        const SampleDev& sd = s[i].dev;
+        if (sd.variant < 0) return false;
+        if (sd.stride * es + 65536 > (int64_t)kOob) return false;
+        if (((int64_t)sd.xwords * sd.ny * sd.nz + 2) * 4 + 65536 > (int64_t)kOob) return false;
+    }
     return true;
 }
 
@@ -615,7 +869,7 @@ inline int64_t zmarch_max_items(const SH* s, int n) {
     for (int i = 0; i < n; ++i) {
         const SampleDev& sd = s[i].dev;
         if (sd.variant < 0) continue;
-        items += (int64_t)sd.tiles_y * ((sd.nz + kTileLZ[0] - 1) / kTileLZ[0]);
+        items += (int64_t)sd.tiles_y * ((sd.nz + tile_lz(0) - 1) / tile_lz(0));
     }
     return items;
 }

@@ -1,0 +1,31 @@
+// tau1_zmarch_inst.hip -- instantiates the z-march kernels of one
+// (lattice, precision) pair, chosen with -DTAU1_Q=.. -DTAU1_P=.. at build time,
+// so the pairs compile in parallel.
+#include "tau1_zmarch.hpp"
+
+#ifndef TAU1_Q
+#error "TAU1_Q must be defined"
+#endif
+#ifndef TAU1_P
+#error "TAU1_P must be defined"
+#endif
+
+namespace tau1 {
+
+#define TAU1_CAT2(a, b, c) a##b##_##c
+#define TAU1_CAT(a, b, c) TAU1_CAT2(a, b, c)
+
+void* TAU1_CAT(zm_kernel_, TAU1_Q, TAU1_P)(int variant, bool hoist) {
+#define TAU1_K(V, H) reinterpret_cast<void*>(&k_zmarch<TAU1_Q, TAU1_P, V, H>)
+    if (variant < 0) return TAU1_K(-1, false);
+    switch (variant) {
+#define TAU1_V(V) case V: return hoist ? TAU1_K(V, true) : TAU1_K(V, false);
+        TAU1_V(0) TAU1_V(1) TAU1_V(2) TAU1_V(3) TAU1_V(4) TAU1_V(5) TAU1_V(6) TAU1_V(7)
+        TAU1_V(8) TAU1_V(9) TAU1_V(10) TAU1_V(11) TAU1_V(12) TAU1_V(13) TAU1_V(14)
+#undef TAU1_V
+    }
+#undef TAU1_K
+    return nullptr;
+}
+
+}  // namespace tau1

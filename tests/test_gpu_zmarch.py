@@ -19,21 +19,23 @@ def bounds(prec, u_scale):
     return {"drho_abs": (2.0 * eps + 16.0 * 2.0 ** -24) * u_scale, "u_rel_l2": 8.0 * eps}
 
 
-# nx values cover every lane layout: 64/G lanes per row x PX nodes per lane
+# nx values cover every lane layout: C chunks x (64/G) lanes x K nodes
 LAYOUT_DIMS = [
-    (64, 5, 7),     # G=1 PX=1
-    (128, 3, 4),    # G=1 PX=2
-    (192, 2, 3),    # G=1 PX=3
-    (256, 3, 2),    # G=1 PX=4
-    (320, 2, 2),    # G=1 PX=5
-    (512, 2, 3),    # G=1 PX=8
-    (32, 9, 4),     # G=2 PX=1
-    (96, 5, 5),     # G=2 PX=3
-    (160, 3, 3),    # G=2 PX=5
-    (224, 3, 2),    # G=2 PX=7
-    (288, 3, 2),    # G=2 PX=9
-    (16, 6, 5),     # G=4 PX=1
-    (48, 7, 3),     # G=4 PX=3
+    (64, 5, 7),     # G=1 C=1 K=1
+    (128, 3, 4),    # G=1 C=1 K=2
+    (192, 2, 3),    # G=1 C=1 K=3
+    (256, 3, 2),    # G=1 C=1 K=4
+    (320, 2, 2),    # G=1 C=1 K=5
+    (384, 2, 3),    # G=1 C=2 K=3
+    (512, 2, 3),    # G=1 C=2 K=4
+    (32, 9, 4),     # G=2 C=1 K=1
+    (96, 5, 5),     # G=2 C=1 K=3
+    (160, 3, 3),    # G=2 C=1 K=5
+    (224, 3, 2),    # G=2 C=1 K=7
+    (288, 3, 2),    # G=2 C=3 K=3
+    (16, 6, 5),     # G=4 C=1 K=1
+    (48, 7, 3),     # G=4 C=1 K=3
+    (80, 5, 3),     # G=4 C=1 K=5
 ]
 
 
