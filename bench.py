@@ -1,0 +1,386 @@
+#!/usr/bin/env python3
+"""Throughput of the Tau1 stream-and-collide step on one MI355X.
+
+One step is one pass of the whole update (gather / equilibrium / accumulate,
+bounce-back, forcing, finalise, store) over every sample of the workload, with
+the state resident in HBM.  Throughput is fluid lattice updates per second
+(GFLUPS, the paper's FLUPS measure of the performance section) and the share
+of the 8 TB/s HBM peak taken by the algorithmic traffic of 2 (d+1) s bytes per
+fluid node plus one mask bit per node (complexity table of the paper).
+
+Sections (``--sections``, default all):
+  main       D3Q19, 512^3 sphere packing (r = 12, porosity 0.7, seed 3000),
+             FP32, g = 1e-6 along x; timed for exactly ``--steps`` steps.  This
+             is the headline value and carries the roofline object.
+  lattices   D3Q15 and D3Q27 on the same geometry (500 steps each).
+  precision  D3Q19 512^3 porosity 0.6 (r = 12, seed 4000) with (rho - 1, u)
+             stored in FP32, FP16 (scaled) and BF16, 2000 steps each; error of
+             each mode on the 128^3 crop after 2000 steps against the FP64 mode
+             of the library (and against the FP64 oracle with
+             ``--oracle-accuracy``, which takes minutes of CPU time).
+  batch      64 uneven porous samples (sides 64..320, porosity U[0.4, 0.95],
+             radius U[4, 16], seeds 5000+i) in one launch per step, 100-step
+             graphs, autotuned tiles, 1000 steps; against the same samples run
+             one by one.
+The oracle leg (``cpu_baseline``) times the FP64 CPU oracle on a few steps of
+the main workload on the host cores.
+
+Prints ONE JSON line on stdout; progress goes to stderr.  Only one GPU is
+used: ``--gpus`` above 1 exits with a message.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "Tau1 D3Q19 GFLUPS + % HBM roofline: FP32 vs 16-bit storage vs batched"
+PEAK_HBM_GBS = 8000.0          # MI355X HBM3E, published
+G_MAIN = (1e-6, 0.0, 0.0)
+COUNTERS = os.path.join(ROOT, "profiles", "zmarch_d3q19_f32_512cube_phi07.counters.txt")
+KERNEL_SOURCES = ("tau1_device.hpp", "tau1_kernels.hpp", "tau1_zmarch.hpp",
+                  "tau1_zmarch_inst.hip")
+
+
+def log(msg: str):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def parse_args(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=500, help="timed steps of the main workload")
+    ap.add_argument("--warmup", type=int, default=100, help="untimed steps before timing")
+    ap.add_argument("--sections", default="main,lattices,precision,batch")
+    ap.add_argument("--tile", type=int, default=-1, help="z-march tile; -1 = autotune")
+    ap.add_argument("--graph-chunk", type=int, default=100)
+    ap.add_argument("--lattice-steps", type=int, default=500)
+    ap.add_argument("--precision-steps", type=int, default=2000)
+    ap.add_argument("--batch-steps", type=int, default=1000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--oracle-accuracy", action="store_true",
+                    help="also compare the 128^3 crop with the FP64 oracle (slow)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run the copy kernel (for counter calibration)")
+    return ap.parse_args(argv)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2312_14742_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    with open(os.path.join(ROOT, "paper_2312_14742_amd", "build.py"), "rb") as f:
+        h.update(f.read())
+    return h.hexdigest()
+
+
+def read_counters():
+    """HBM bytes per launch recorded by rocprofv3 for the main kernel, or None."""
+    if not os.path.exists(COUNTERS):
+        return None
+    vals = {}
+    with open(COUNTERS) as f:
+        for line in f:
+            if line.startswith("#") or ":" not in line:
+                continue
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    return vals
+
+
+# ---------------------------------------------------------------------------
+def gen_inputs(args, sections):
+    from paper_2312_14742_amd import inputs
+    geos = {}
+    if "main" in sections or "lattices" in sections:
+        t = time.perf_counter()
+        geos["main"] = inputs.spheres(512, 512, 512, 12.0, 0.7, seed=3000)
+        log(f"main geometry: porosity {geos['main'].porosity:.5f}, "
+            f"{geos['main'].spheres} spheres ({time.perf_counter() - t:.1f} s)")
+    if "precision" in sections:
+        t = time.perf_counter()
+        geos["prec"] = inputs.spheres(512, 512, 512, 12.0, 0.6, seed=4000)
+        log(f"precision geometry: porosity {geos['prec'].porosity:.5f} "
+            f"({time.perf_counter() - t:.1f} s)")
+    if "batch" in sections:
+        t = time.perf_counter()
+        workers = max(1, min(16, os.cpu_count() or 1))
+        geos["batch"] = inputs.batch_recipe(64, 5000, workers=workers)
+        log(f"batch: {len(geos['batch'])} samples, "
+            f"{sum(b.side ** 3 for b in geos['batch'])} nodes ({time.perf_counter() - t:.1f} s)")
+    return geos
+
+
+def cpu_baseline(geo):
+    """FP64 oracle on the host cores: a few steps of the main lattice."""
+    import oracle
+    st = oracle.State(geo.solid)
+    nf = geo.n_fluid
+    t = time.perf_counter()
+    st = oracle.run(19, st, G_MAIN, 1)
+    t1 = time.perf_counter() - t
+    n = int(max(1, min(6, 12.0 / max(t1, 1e-3))))
+    t = time.perf_counter()
+    oracle.run(19, st, G_MAIN, n)
+    tn = time.perf_counter() - t
+    cores = oracle.threads()
+    log(f"oracle: {n} steps in {tn:.1f} s on {cores} threads")
+    return {"value": nf * n / tn / 1e9, "unit": "GFLUPS", "cores": cores, "kind": "oracle",
+            "sample": f"{n} steps (after 1 warm-up step) of the full 512^3 porosity-0.7 "
+                      f"D3Q19 lattice, FP64 oracle, OpenMP over z-planes, "
+                      f"{tn:.1f} s"}
+
+
+class GpuRunner:
+    def __init__(self):
+        import torch
+        if not torch.cuda.is_available():
+            raise SystemExit("bench.py needs a ROCm GPU (torch.cuda is unavailable)")
+        from paper_2312_14742_amd import tau1
+        self.torch = torch
+        self.tau1 = tau1
+        self.device = torch.device("cuda:0")
+        torch.cuda.set_device(self.device)
+
+    def make(self, samples, lattice, precision, g, graph_chunk, tile, kernel=-1,
+             f16_scales=(0, 0)):
+        sim = self.tau1.Sim(samples, lattice=lattice, precision=precision, g=g,
+                            graph_chunk=graph_chunk, kernel=kernel, tile=tile,
+                            f16_scales=f16_scales)
+        if tile < 0 and kernel != 0:
+            sim.autotune(10)
+        return sim
+
+    def time_steps(self, sim, steps, warmup):
+        """Wall and HIP-event time of exactly `steps` steps on the sim's stream."""
+        torch = self.torch
+        sim.step(warmup)
+        sim.sync()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        e0.record(sim.stream)
+        sim.step(steps)
+        e1.record(sim.stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        sim.sync()
+        ev = e0.elapsed_time(e1) * 1e-3
+        return wall, ev
+
+    def case(self, samples, lattice, precision, steps, warmup, graph_chunk, tile,
+             g=G_MAIN, label=""):
+        sim = self.make(samples, lattice, precision, g, graph_chunk, tile)
+        wall, ev = self.time_steps(sim, steps, warmup)
+        inf = sim.info()
+        res = {
+            "gflups": inf["n_fluid"] * steps / wall / 1e9,
+            "ms_per_step": wall / steps * 1e3,
+            "launch_ms": ev / steps * 1e3,
+            "alg_gbs": inf["bytes_per_step"] / (ev / steps) / 1e9,
+            "tile": inf["tile"], "kernel": inf["kernel"],
+            "n_fluid": inf["n_fluid"], "n_nodes": inf["n_nodes"],
+            "bytes_per_step": inf["bytes_per_step"],
+        }
+        res["frac"] = res["alg_gbs"] / PEAK_HBM_GBS
+        log(f"{label}: {res['gflups']:.2f} GFLUPS, {res['alg_gbs']:.0f} GB/s algorithmic "
+            f"({100 * res['frac']:.1f}% of 8 TB/s), tile {res['tile']}")
+        return sim, res
+
+    def copy_gbs(self, nbytes):
+        sec = self.tau1.copy_probe(nbytes, reps=10)
+        return nbytes / sec / 1e9   # read nbytes/2 + write nbytes/2
+
+
+def rel_l2(a, b, mask):
+    import numpy as np
+    d = (a - b)[:, mask]
+    r = b[:, mask]
+    return float(np.sqrt((d * d).sum() / max((r * r).sum(), 1e-300)))
+
+
+def precision_section(gr, geo, args, out):
+    import numpy as np
+    from paper_2312_14742_amd import tau1
+    modes = {}
+    for prec in ("f32", "f16", "bf16"):
+        sim, res = gr.case([tau1.Sample(geo.solid)], 19, prec, args.precision_steps,
+                           args.warmup, args.graph_chunk, -1, label=f"precision {prec}")
+        sim.close()
+        modes[prec] = res
+    # accuracy on the 128^3 crop of the same mask (run periodic), 2000 steps
+    crop = np.ascontiguousarray(geo.solid[:128, :128, :128])
+    fluid = crop == 0
+    steps = 2000
+    ref = gr.make([tau1.Sample(crop)], 19, "f64", G_MAIN, args.graph_chunk, -1)
+    ref.step(steps)
+    _, u_ref = ref.moments(0)
+    k_ref, m_ref = ref.permeability(0, 0)
+    ref.close()
+    m0 = float(fluid.sum())
+    for prec in ("f64", "f32", "f16", "bf16"):
+        sim = gr.make([tau1.Sample(crop)], 19, prec, G_MAIN, args.graph_chunk, -1)
+        sim.step(steps)
+        _, u = sim.moments(0, allow_nonfinite=True)
+        k, m = sim.permeability(0, 0)
+        sim.close()
+        acc = {"u_rel_l2_vs_gpu_f64": rel_l2(u, u_ref, fluid),
+               "k_rel_err_vs_gpu_f64": abs(k - k_ref) / abs(k_ref),
+               "mass_drift": (m - m0) / m0}
+        modes.setdefault(prec, {})["crop128_2000_steps"] = acc
+        log(f"crop accuracy {prec}: {acc}")
+    if args.oracle_accuracy:
+        import oracle
+        t = time.perf_counter()
+        st = oracle.run(19, oracle.State(crop), G_MAIN, steps)
+        m_o, k_o = oracle.reduce(st, 0, G_MAIN[0])
+        log(f"oracle crop run {time.perf_counter() - t:.0f} s")
+        for prec in ("f64", "f32", "f16", "bf16"):
+            sim = gr.make([tau1.Sample(crop)], 19, prec, G_MAIN, args.graph_chunk, -1)
+            sim.step(steps)
+            _, u = sim.moments(0, allow_nonfinite=True)
+            k, m = sim.permeability(0, 0)
+            sim.close()
+            modes[prec]["crop128_2000_steps"].update({
+                "u_rel_l2_vs_oracle": rel_l2(u, st.u, fluid),
+                "k_rel_err_vs_oracle": abs(k - k_o) / abs(k_o),
+                "mass_drift_oracle": (m_o - m0) / m0})
+    out["precision_modes"] = {
+        "workload": "D3Q19 512^3 sphere packing r=12 porosity 0.6 seed 4000, g=1e-6 x, "
+                    f"{args.precision_steps} steps per mode; accuracy on the 128^3 crop "
+                    "after 2000 steps",
+        "modes": modes}
+
+
+def batch_section(gr, batch, args, out):
+    from paper_2312_14742_amd import tau1
+    samples = [tau1.Sample(b.geometry.solid) for b in batch]
+    steps = args.batch_steps
+    sim, res = gr.case(samples, 19, "f32", steps, args.graph_chunk, args.graph_chunk, -1,
+                       label="batched 64 samples")
+    probe = [0, max(range(len(batch)), key=lambda i: batch[i].side)]
+    batched_state = {i: sim.moments(i) for i in probe}
+    sim.close()
+    solo_time = 0.0
+    solo_ev = 0.0
+    nf_total = 0
+    bitwise = True
+    for i, s in enumerate(samples):
+        solo = gr.make([s], 19, "f32", G_MAIN, args.graph_chunk, -1)
+        wall, ev = gr.time_steps(solo, steps, args.graph_chunk)
+        solo_time += wall
+        solo_ev += ev
+        nf_total += solo.info()["n_fluid"]
+        if i in probe:
+            d, u = solo.moments(0)
+            bd, bu = batched_state[i]
+            bitwise &= d.tobytes() == bd.tobytes() and u.tobytes() == bu.tobytes()
+        solo.close()
+    res["one_by_one_gflups"] = nf_total * steps / solo_time / 1e9
+    res["one_by_one_ms_per_step"] = solo_time / steps * 1e3
+    res["speedup_vs_one_by_one"] = res["gflups"] / res["one_by_one_gflups"]
+    res["bitwise_equal_to_solo"] = {"samples_checked": probe, "equal": bool(bitwise)}
+    res["workload"] = (f"64 samples, sides 64+32*integers(0,9), porosity U[0.4,0.95], "
+                       f"radius U[4,16], seeds 5000+i; D3Q19 FP32; {steps} steps in "
+                       f"{args.graph_chunk}-step graphs (warm-up {args.graph_chunk} steps, "
+                       "also for each solo run)")
+    log(f"one by one: {res['one_by_one_gflups']:.2f} GFLUPS; batched speedup "
+        f"{res['speedup_vs_one_by_one']:.2f}x; bitwise {bitwise}")
+    out["batched"] = res
+
+
+def main(argv=None):
+    args = parse_args(argv)
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py runs on exactly one GPU: the Tau1 path here is built and measured on "
+              "a single MI355X (multi-GPU sharding is a design note only). "
+              f"Got --gpus {args.gpus}, WORLD_SIZE {world}.", file=sys.stderr)
+        return 2
+    if args.copy_calibration:
+        gr = GpuRunner()
+        nbytes = 2 << 30
+        gbs = gr.copy_gbs(nbytes)
+        print(json.dumps({"copy_kernel": "k_copy16", "bytes_read_per_launch": nbytes // 2,
+                          "bytes_written_per_launch": nbytes // 2, "gbs": gbs}), flush=True)
+        return 0
+    sections = [s.strip() for s in args.sections.split(",") if s.strip()]
+    geos = gen_inputs(args, sections)
+    out = {}
+    cpu = None
+    if "main" in sections and not args.no_cpu_baseline:
+        cpu = cpu_baseline(geos["main"])
+
+    gr = GpuRunner()
+    from paper_2312_14742_amd import tau1
+    main_res = None
+    if "main" in sections:
+        sim, main_res = gr.case([tau1.Sample(geos["main"].solid)], 19, "f32", args.steps,
+                                args.warmup, args.graph_chunk, args.tile, label="main D3Q19 f32")
+        sim.close()
+        copy_bytes = 2 * 16 * main_res["n_nodes"]
+        main_res["copy_gbs"] = gr.copy_gbs(copy_bytes)
+        main_res["frac_of_copy"] = main_res["alg_gbs"] / main_res["copy_gbs"]
+        log(f"copy kernel {main_res['copy_gbs']:.0f} GB/s over {copy_bytes / 1e9:.2f} GB")
+    if "lattices" in sections:
+        sweep = {}
+        for q in (15, 27):
+            sim, r = gr.case([tau1.Sample(geos["main"].solid)], q, "f32", args.lattice_steps,
+                             args.warmup, args.graph_chunk, -1, label=f"D3Q{q} f32")
+            sim.close()
+            sweep[f"D3Q{q}"] = r
+        if main_res is not None:
+            sweep["D3Q19"] = {k: main_res[k] for k in ("gflups", "alg_gbs", "frac", "tile",
+                                                       "ms_per_step")}
+        out["lattice_sweep"] = {"workload": "512^3 sphere packing r=12 porosity 0.7 seed "
+                                            f"3000, FP32, {args.lattice_steps} steps",
+                                "lattices": sweep}
+    if "precision" in sections:
+        precision_section(gr, geos["prec"], args, out)
+    if "batch" in sections:
+        batch_section(gr, geos["batch"], args, out)
+
+    line = {"metric": METRIC, "higher_is_better": True, "n_gpus": 1, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "steps": args.steps, "warmup": args.warmup}
+    if main_res is not None:
+        geo = geos["main"]
+        traffic = None
+        cnt = read_counters()
+        if (cnt and cnt.get("source_sha256") == kernel_source_hash()
+                and int(cnt.get("tile", -99)) == main_res["tile"]):
+            traffic = float(cnt["hbm_bytes_per_launch"])
+        line.update({
+            "value": main_res["gflups"], "unit": "GFLUPS",
+            "ms_per_step": main_res["ms_per_step"],
+            "config": {"workload": "Tau1 D3Q19 FP32, 512^3 periodic sphere packing "
+                                   "(r=12, target porosity 0.7, seed 3000), g=1e-6 along x",
+                       "nx": 512, "ny": 512, "nz": 512, "porosity": geo.porosity,
+                       "n_fluid": main_res["n_fluid"], "tile": main_res["tile"],
+                       "graph_chunk": args.graph_chunk},
+            "roofline": {"bound": "hbm", "achieved": main_res["alg_gbs"],
+                         "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": main_res["frac"],
+                         "traffic": traffic,
+                         "alg_bytes_per_launch": main_res["bytes_per_step"],
+                         "launch_ms": main_res["launch_ms"],
+                         "kernel": "tau1::k_zmarch (one launch per step)",
+                         "copy_gbs": main_res["copy_gbs"],
+                         "frac_of_copy": main_res["frac_of_copy"]},
+        })
+    line["cpu_baseline"] = cpu
+    line.update(out)
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -679,10 +679,7 @@ tau1_status tau1_copy_probe(void* hip_stream, void* buf, size_t bytes, int32_t r
     const int64_t n = (int64_t)(bytes / 2 / 16);
     const float4* src = reinterpret_cast<const float4*>(buf);
     float4* dst = reinterpret_cast<float4*>(reinterpret_cast<uint8_t*>(buf) + n * 16);
-    int dev = 0, cus = 0;
-    HIP_TRY(hipGetDevice(&dev));
-    HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    const unsigned grid = (unsigned)std::min<int64_t>((n + 255) / 256, (int64_t)cus * 16);
+    const unsigned grid = (unsigned)std::min<int64_t>((n + 255) / 256, (int64_t)1 << 22);
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));

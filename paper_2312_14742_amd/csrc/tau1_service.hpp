@@ -50,10 +50,12 @@ __global__ __launch_bounds__(kReduceThreads) void k_reduce_final(const double* _
     }
 }
 
-// Copy probe: 16-byte vector copy, grid-stride.
-__global__ void k_copy16(const float4* __restrict__ src, float4* __restrict__ dst, int64_t n) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x)
+// Copy probe: one 16-byte vector per thread (the grid covers the array; the
+// stride loop only runs for arrays beyond 2^30 vectors).
+__global__ __launch_bounds__(256) void k_copy16(const float4* __restrict__ src,
+                                                float4* __restrict__ dst, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * 256)
         dst[i] = src[i];
 }
 

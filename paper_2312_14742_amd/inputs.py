@@ -128,26 +128,34 @@ class BatchSample:
     radius: float
 
 
+def _batch_one(args):
+    seed, sides = args
+    rng = np.random.Generator(np.random.PCG64(seed))
+    side = 64 + 32 * int(rng.integers(0, 9))
+    if sides is not None:
+        side = int(sides(side))
+    target = float(rng.uniform(0.4, 0.95))
+    radius = float(rng.uniform(4.0, 16.0))
+    geo = spheres(side, side, side, radius, target, seed, rng=rng)
+    return BatchSample(geo, side, target, radius)
+
+
 def batch_recipe(n_samples: int = 64, seed0: int = 5000,
-                 sides=None) -> list[BatchSample]:
+                 sides=None, workers: int = 1) -> list[BatchSample]:
     """Uneven porous samples for the batched path.
 
     Per sample i, from PCG64(seed0 + i) in this order: side = 64 + 32 *
     integers(0, 9); target porosity ~ U[0.4, 0.95]; radius ~ U[4, 16]; then
     the sphere centres.  ``sides`` (optional) caps the sides for small tests.
+    ``workers`` > 1 draws the samples in a process pool (same results: each
+    sample depends only on its own seed); call it before any GPU use.
     """
-    out = []
-    for i in range(n_samples):
-        seed = seed0 + i
-        rng = np.random.Generator(np.random.PCG64(seed))
-        side = 64 + 32 * int(rng.integers(0, 9))
-        if sides is not None:
-            side = int(sides(side))
-        target = float(rng.uniform(0.4, 0.95))
-        radius = float(rng.uniform(4.0, 16.0))
-        geo = spheres(side, side, side, radius, target, seed, rng=rng)
-        out.append(BatchSample(geo, side, target, radius))
-    return out
+    jobs = [(seed0 + i, sides) for i in range(n_samples)]
+    if workers <= 1 or sides is not None:
+        return [_batch_one(j) for j in jobs]
+    import multiprocessing as mp
+    with mp.get_context("fork").Pool(workers) as pool:
+        return pool.map(_batch_one, jobs, chunksize=1)
 
 
 def random_state(nx: int, ny: int, nz: int, seed: int, solid_frac: float = 0.3,
