@@ -7,9 +7,9 @@ import numpy as np
 import oracle
 from paper_2312_14742_amd import tau1
 
-# Tolerances of the HIP path against the FP64 oracle ("Parity
-# bar").  FP64: the benchmark spec's bound.  Reduced modes: normwise bounds derived
-# from the storage rounding unit and the number of steps.
+# Tolerance of the HIP path against the FP64 oracle in FP64 mode (normwise:
+# absolute on rho, relative to max|u| on u).  The reduced-precision modes use
+# bounds derived from the storage rounding unit, written in their tests.
 TOL_F64 = 1e-12
 
 
