@@ -107,6 +107,13 @@ Plan make_plan(const tau1_desc* d) {
         off = align_up(off + sizeof(uint32_t) * (size_t)sd.words * sd.ny * sd.nz, kAlign);
         sd.xmask = (int64_t)off;
         off = align_up(off + sizeof(uint32_t) * ((size_t)sd.xwords * sd.ny * sd.nz + 2), kAlign);
+        if (sd.variant >= 0) {
+            // wall list: row offsets, then at most one entry per node
+            sd.wall_off = (int64_t)off;
+            off = align_up(off + sizeof(uint32_t) * ((size_t)sd.ny * sd.nz + 1), kAlign);
+            sd.wall_list = (int64_t)off;
+            off = align_up(off + (d->lattice == 27 ? 8 : 4) * (size_t)sd.n + 8, kAlign);
+        }
         for (int b = 0; b < 2; ++b) {
             sd.state[b] = (int64_t)off;
             off = align_up(off + (size_t)4 * sd.stride * sz, kAlign);
@@ -138,6 +145,12 @@ struct tau1_ctx {
     size_t ws_bytes = 0;
     Plan plan;
     StepArgs args[2];
+    // z-march launches: one per lane layout present, each over its samples' items
+    struct ZGroup {
+        int variant;
+        StepArgs args[2];
+    };
+    std::vector<ZGroup> zgroups;
     int parity = 0;
     int64_t steps_done = 0;
     int64_t n_nodes = 0, n_fluid = 0;
@@ -195,14 +208,15 @@ bool zmarch_eligible(const tau1_ctx* ctx) {
                             (int)ctx->plan.s.size());
 }
 
-Launch step_launch(const tau1_ctx* ctx, int kernel, int tile) {
+// Launch geometry of one step kernel: z-march group g (kernel 1) or the
+// per-node gather over every sample (kernel 0).
+Launch step_launch(const tau1_ctx* ctx, int kernel, int tile, int g) {
     Launch l{};
     if (kernel == 1) {
-        l.fn = pick_zmarch(ctx->lattice, ctx->precision,
-                           common_variant(ctx->plan.s.data(), (int)ctx->plan.s.size()),
-                           tile_hoist(tile));
+        const auto& grp = ctx->zgroups[g];
+        l.fn = pick_zmarch(ctx->lattice, ctx->precision, grp.variant, tile_hoist(tile));
         l.block = dim3(zmarch_threads(tile));
-        l.grid = dim3((unsigned)zmarch_grid(ctx->args[0].ntiles, tile));
+        l.grid = dim3((unsigned)zmarch_grid(grp.args[0].ntiles, tile));
         l.shmem = 0;
     } else {
         l.fn = pick_gather(ctx->lattice, ctx->precision);
@@ -213,12 +227,23 @@ Launch step_launch(const tau1_ctx* ctx, int kernel, int tile) {
     return l;
 }
 
-tau1_status launch_one(tau1_ctx* ctx, int kernel, int tile, const StepArgs& a) {
-    const Launch l = step_launch(ctx, kernel, tile);
-    if (!l.fn) return TAU1_E_UNSUPPORTED;
-    if (l.grid.x == 0) return TAU1_OK;
-    void* params[] = {const_cast<StepArgs*>(&a)};
-    HIP_TRY(hipLaunchKernel(l.fn, l.grid, l.block, params, l.shmem, ctx->stream));
+int launch_groups(const tau1_ctx* ctx, int kernel) {
+    return kernel == 1 ? (int)ctx->zgroups.size() : 1;
+}
+
+StepArgs* launch_args(tau1_ctx* ctx, int kernel, int g, int parity) {
+    return kernel == 1 ? &ctx->zgroups[g].args[parity] : &ctx->args[parity];
+}
+
+// One time step reading buffer `parity`: every launch of the step in order.
+tau1_status launch_one(tau1_ctx* ctx, int kernel, int tile, int parity) {
+    for (int g = 0; g < launch_groups(ctx, kernel); ++g) {
+        const Launch l = step_launch(ctx, kernel, tile, g);
+        if (!l.fn) return TAU1_E_UNSUPPORTED;
+        if (l.grid.x == 0) continue;
+        void* params[] = {launch_args(ctx, kernel, g, parity)};
+        HIP_TRY(hipLaunchKernel(l.fn, l.grid, l.block, params, l.shmem, ctx->stream));
+    }
     return TAU1_OK;
 }
 
@@ -230,34 +255,88 @@ void destroy_graph(tau1_ctx* ctx) {
     ctx->graph_kernel = ctx->graph_tile = -1;
 }
 
-// Graph of graph_chunk single-step kernel nodes in a chain; the parity
-// alternates node by node and, graph_chunk being even, the graph maps the
-// current buffer onto itself.  Built without stream capture.
+// Graph of graph_chunk time steps: one chain of single-step kernel nodes per
+// launch group (z-march lane layout); the chains share no samples, so they
+// are independent of each other.  The parity alternates node by node and,
+// graph_chunk being even, the graph maps the current buffer onto itself.
+// Built without stream capture.
 tau1_status build_graph(tau1_ctx* ctx) {
     destroy_graph(ctx);
-    const Launch l = step_launch(ctx, ctx->kernel, ctx->tile);
-    if (!l.fn) return TAU1_E_UNSUPPORTED;
     HIP_TRY(hipGraphCreate(&ctx->graph, 0));
-    hipGraphNode_t prev = nullptr;
-    for (int s = 0; s < ctx->graph_chunk; ++s) {
-        StepArgs* a = &ctx->args[(ctx->parity + s) & 1];
-        void* params[] = {a};
-        hipKernelNodeParams kp{};
-        kp.func = l.fn;
-        kp.gridDim = l.grid;
-        kp.blockDim = l.block;
-        kp.sharedMemBytes = (unsigned)l.shmem;
-        kp.kernelParams = params;
-        kp.extra = nullptr;
-        hipGraphNode_t node;
-        HIP_TRY(hipGraphAddKernelNode(&node, ctx->graph, prev ? &prev : nullptr, prev ? 1 : 0, &kp));
-        prev = node;
+    const int ng = launch_groups(ctx, ctx->kernel);
+    for (int g = 0; g < ng; ++g) {
+        const Launch l = step_launch(ctx, ctx->kernel, ctx->tile, g);
+        if (!l.fn) return TAU1_E_UNSUPPORTED;
+        if (l.grid.x == 0) continue;
+        hipGraphNode_t prev = nullptr;
+        for (int s = 0; s < ctx->graph_chunk; ++s) {
+            void* params[] = {launch_args(ctx, ctx->kernel, g, (ctx->parity + s) & 1)};
+            hipKernelNodeParams kp{};
+            kp.func = l.fn;
+            kp.gridDim = l.grid;
+            kp.blockDim = l.block;
+            kp.sharedMemBytes = (unsigned)l.shmem;
+            kp.kernelParams = params;
+            kp.extra = nullptr;
+            hipGraphNode_t node;
+            HIP_TRY(hipGraphAddKernelNode(&node, ctx->graph, prev ? &prev : nullptr, prev ? 1 : 0,
+                                          &kp));
+            prev = node;
+        }
     }
     HIP_TRY(hipGraphInstantiate(&ctx->exec, ctx->graph, nullptr, nullptr, 0));
     ctx->graph_kernel = ctx->kernel;
     ctx->graph_tile = ctx->tile;
     ctx->graph_parity = ctx->parity;
     return TAU1_OK;
+}
+
+// Wall list of one sample (z-march samples only): count per row on the GPU,
+// exclusive scan of the row counts on the host, fill on the GPU.
+template <int Q>
+tau1_status build_wall_list_q(tau1_ctx* ctx, const SampleDev& sd) {
+    const int64_t rows = (int64_t)sd.ny * sd.nz;
+    uint32_t* off = reinterpret_cast<uint32_t*>(ctx->base + sd.wall_off);
+    const uint32_t* xm = reinterpret_cast<const uint32_t*>(ctx->base + sd.xmask);
+    using E = typename WallEntry<Q>::type;
+    E* list = reinterpret_cast<E*>(ctx->base + sd.wall_list);
+    const unsigned grid = (unsigned)((rows + 255) / 256);
+    hipLaunchKernelGGL(k_wall_count<Q>, dim3(grid), dim3(256), 0, ctx->stream, xm, sd.nx, sd.ny,
+                       sd.nz, sd.xwords, off);
+    HIP_TRY(hipGetLastError());
+    std::vector<uint32_t> h;
+    try {
+        h.resize((size_t)rows + 1);
+    } catch (const std::bad_alloc&) {
+        return TAU1_E_NOMEM;
+    }
+    HIP_TRY(hipMemcpyAsync(h.data(), off, sizeof(uint32_t) * rows, hipMemcpyDeviceToHost,
+                           ctx->stream));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    uint64_t acc = 0;
+    for (int64_t r = 0; r < rows; ++r) {
+        const uint32_t c = h[r];
+        h[r] = (uint32_t)acc;
+        acc += c;
+    }
+    if (acc > (uint64_t)sd.n) return TAU1_E_INVALID;  // cannot happen: one entry per node at most
+    h[rows] = (uint32_t)acc;
+    HIP_TRY(hipMemcpyAsync(off, h.data(), sizeof(uint32_t) * (rows + 1), hipMemcpyHostToDevice,
+                           ctx->stream));
+    hipLaunchKernelGGL((k_wall_fill<Q, E>), dim3(grid), dim3(256), 0, ctx->stream, xm, sd.nx,
+                       sd.ny, sd.nz, sd.xwords, kVariants[sd.variant].g, off, list);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    return TAU1_OK;
+}
+
+tau1_status build_wall_list(tau1_ctx* ctx, const SampleDev& sd) {
+    switch (ctx->lattice) {
+        case 15: return build_wall_list_q<15>(ctx, sd);
+        case 19: return build_wall_list_q<19>(ctx, sd);
+        case 27: return build_wall_list_q<27>(ctx, sd);
+    }
+    return TAU1_E_INVALID;
 }
 
 template <int P>
@@ -288,6 +367,10 @@ tau1_status upload_sample_t(tau1_ctx* ctx, int s, const tau1_sample& in) {
         HIP_TRY(hipGetLastError());
         HIP_TRY(hipMemsetAsync(xm + nt, 0, 2 * sizeof(uint32_t), ctx->stream));
         HIP_TRY(hipStreamSynchronize(ctx->stream));
+    }
+    if (sd.variant >= 0) {
+        const tau1_status st = build_wall_list(ctx, sd);
+        if (st != TAU1_OK) return st;
     }
     // state
     for (int64_t i0 = 0; i0 < n; i0 += chunk) {
@@ -373,7 +456,29 @@ tau1_status reduce_t(tau1_ctx* ctx, int s, int axis, double out[4]) {
 // Selects the z-march tile (z-segment length), rebuilds and uploads the work
 // list; cached graphs are rebuilt on the next step.
 tau1_status set_tile(tau1_ctx* ctx, int tile) {
-    std::vector<int32_t> tl = zmarch_worklist(ctx->plan.s.data(), ctx->nsamples, tile_lz(tile));
+    // lane layouts present, in order of first appearance
+    std::vector<int> layouts;
+    for (const auto& sh : ctx->plan.s)
+        if (sh.dev.variant >= 0 &&
+            std::find(layouts.begin(), layouts.end(), sh.dev.variant) == layouts.end())
+            layouts.push_back(sh.dev.variant);
+    std::vector<int32_t> tl;
+    std::vector<tau1_ctx::ZGroup> groups;
+    for (int v : layouts) {
+        const int64_t item0 = (int64_t)tl.size() / 4;
+        std::vector<int32_t> part =
+            zmarch_worklist(ctx->plan.s.data(), ctx->nsamples, tile_lz(tile), v);
+        tl.insert(tl.end(), part.begin(), part.end());
+        tau1_ctx::ZGroup g;
+        g.variant = v;
+        for (int p = 0; p < 2; ++p) {
+            g.args[p] = ctx->args[p];
+            g.args[p].tiles = reinterpret_cast<const int32_t*>(ctx->base + ctx->plan.tiles_off) +
+                              4 * item0;
+            g.args[p].ntiles = (int32_t)((int64_t)tl.size() / 4 - item0);
+        }
+        groups.push_back(g);
+    }
     const int64_t items = (int64_t)tl.size() / 4;
     if (items > ctx->plan.ntiles) return TAU1_E_INVALID;
     if (!tl.empty()) {
@@ -381,9 +486,10 @@ tau1_status set_tile(tau1_ctx* ctx, int tile) {
                                sizeof(int32_t) * tl.size(), hipMemcpyHostToDevice, ctx->stream));
         HIP_TRY(hipStreamSynchronize(ctx->stream));
     }
+    destroy_graph(ctx);
+    ctx->zgroups.swap(groups);
     ctx->args[0].ntiles = ctx->args[1].ntiles = (int32_t)items;
     ctx->tile = tile;
-    destroy_graph(ctx);
     return TAU1_OK;
 }
 
@@ -555,7 +661,7 @@ tau1_status tau1_step(tau1_ctx* ctx, int64_t nsteps) {
         }
     }
     while (nsteps > 0) {
-        st = launch_one(ctx, ctx->kernel, ctx->tile, ctx->args[ctx->parity]);
+        st = launch_one(ctx, ctx->kernel, ctx->tile, ctx->parity);
         if (st != TAU1_OK) return st;
         ctx->parity ^= 1;
         --nsteps;
@@ -623,11 +729,11 @@ tau1_status tau1_autotune(tau1_ctx* ctx, int32_t trial_steps) {
         st = set_tile(ctx, t);
         if (st != TAU1_OK) break;
         // the trial reads the current buffer and writes the spare one only
-        st = launch_one(ctx, 1, t, ctx->args[ctx->parity]);
+        st = launch_one(ctx, 1, t, ctx->parity);
         if (st != TAU1_OK) break;
         HIP_TRY(hipEventRecord(e0, ctx->stream));
         for (int i = 0; i < trial_steps && st == TAU1_OK; ++i)
-            st = launch_one(ctx, 1, t, ctx->args[ctx->parity]);
+            st = launch_one(ctx, 1, t, ctx->parity);
         HIP_TRY(hipEventRecord(e1, ctx->stream));
         HIP_TRY(hipEventSynchronize(e1));
         float ms = 0;

@@ -11,6 +11,8 @@
 #include <hip/hip_bf16.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace tau1 {
 
 // ---------------------------------------------------------------------------
@@ -120,6 +122,13 @@ inline constexpr int storage_bytes(int prec) {
 // the workspace base.  State buffer b (0 or 1) holds four arrays of `stride`
 // elements: drho | vx | vy | vz.
 // ---------------------------------------------------------------------------
+// Wall-list entry: x (bits 0-9), y mod G (10-11), solid-neighbour bit of
+// direction k at bit 11 + k.
+template <int Q>
+struct WallEntry {
+    using type = typename std::conditional<(Q > 19), uint64_t, uint32_t>::type;
+};
+
 struct SampleDev {
     int64_t n;            // nodes
     int64_t stride;       // elements between the four state arrays
@@ -127,6 +136,8 @@ struct SampleDev {
     int64_t mask;         // byte offset of the bit mask (uint32 words)
     int64_t block0;       // first block of this sample in a per-node launch
     int64_t xmask;        // byte offset of the extended (periodic) row mask
+    int64_t wall_off;     // byte offset of the wall-list row offsets (uint32, rows + 1)
+    int64_t wall_list;    // byte offset of the wall-list entries (one per wall node)
     int32_t nx, ny, nz;
     int32_t words;        // mask words per (y, z) row: ceil(nx / 32)
     int32_t xwords;       // extended-mask words per row

@@ -78,4 +78,82 @@ __global__ void k_build_xmask(const uint32_t* __restrict__ mask, uint32_t* __res
     xm[t] = out;
 }
 
+
+// ---------------------------------------------------------------------------
+// Wall list (set-up, once per context): per (y, z) row, one entry for every
+// fluid node with at least one solid lattice neighbour x + c_k (periodic), in
+// increasing x.  The step kernel evaluates halfway bounce-back (Eq. 11) only
+// at these nodes.  Entry bits: 0-9 x, 10-11 y mod G (the row's place in its
+// lane-group block), 12.. one bit per direction k = 1..q-1, set when x + c_k
+// is solid.  uint32 entries for D3Q15/19, uint64 for D3Q27.  One thread per
+// row walks the row's 32-node words using the extended mask (bit e <-> node
+// e - 1, periodic) of the neighbour rows.
+// ---------------------------------------------------------------------------
+template <int Q>
+struct WallRow {
+    uint32_t nb[Q];  // nb[k]: bit j set when node 32 w + j + c_k is solid
+    uint32_t wall;   // fluid nodes of the word with a solid neighbour
+};
+
+template <int Q>
+__device__ __forceinline__ void wall_word(const uint32_t* __restrict__ xm, int nx, int ny, int nz,
+                                          int xwords, int y, int z, int w, WallRow<Q>& out) {
+    using L = Lattice<Q>;
+    auto window = [&](int yy, int zz) -> uint64_t {
+        yy = yy < 0 ? yy + ny : (yy >= ny ? yy - ny : yy);
+        zz = zz < 0 ? zz + nz : (zz >= nz ? zz - nz : zz);
+        const uint32_t* row = xm + ((int64_t)zz * ny + yy) * xwords;
+        // node 32 w + j - 1 sits at bit j of this window
+        return (uint64_t)row[w] | ((uint64_t)row[w + 1] << 32);
+    };
+    uint32_t any = 0;
+    out.nb[0] = 0;
+#pragma unroll
+    for (int k = 1; k < Q; ++k) {
+        const Dir c = L::c[k];
+        out.nb[k] = (uint32_t)(window(y + c.y, z + c.z) >> (1 + c.x));
+        any |= out.nb[k];
+    }
+    const uint32_t own = (uint32_t)(window(y, z) >> 1);
+    const int left = nx - 32 * w;
+    const uint32_t valid = left >= 32 ? 0xffffffffu : ((1u << left) - 1u);
+    out.wall = any & ~own & valid;
+}
+
+template <int Q>
+__global__ void k_wall_count(const uint32_t* __restrict__ xm, int nx, int ny, int nz, int xwords,
+                             uint32_t* __restrict__ count) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= (int64_t)ny * nz) return;
+    const int y = (int)(r % ny), z = (int)(r / ny);
+    uint32_t n = 0;
+    for (int w = 0; w < (nx + 31) / 32; ++w) {
+        WallRow<Q> wr;
+        wall_word<Q>(xm, nx, ny, nz, xwords, y, z, w, wr);
+        n += __builtin_popcount(wr.wall);
+    }
+    count[r] = n;
+}
+
+template <int Q, typename E>
+__global__ void k_wall_fill(const uint32_t* __restrict__ xm, int nx, int ny, int nz, int xwords,
+                            int G, const uint32_t* __restrict__ off, E* __restrict__ list) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= (int64_t)ny * nz) return;
+    const int y = (int)(r % ny), z = (int)(r / ny);
+    uint32_t at = off[r];
+    for (int w = 0; w < (nx + 31) / 32; ++w) {
+        WallRow<Q> wr;
+        wall_word<Q>(xm, nx, ny, nz, xwords, y, z, w, wr);
+        uint32_t b = wr.wall;
+        while (b) {
+            const int j = __builtin_ctz(b);
+            b &= b - 1;
+            E links = 0;
+            for (int k = 1; k < Q; ++k) links |= (E)((wr.nb[k] >> j) & 1u) << (k - 1);
+            list[at++] = (E)(32 * w + j) | ((E)(y % G) << 10) | (links << 12);
+        }
+    }
+}
+
 }  // namespace tau1

@@ -21,12 +21,13 @@
 // momentum are the sums of the equilibria its neighbours send it.
 //
 // Solid nodes hold exact zeros, so as sources they send nothing.  Halfway
-// bounce-back (Eq. (11)) -- a population sent from fluid x towards a solid
+// bounce-back (Eq. 11) -- a population sent from fluid x towards a solid
 // neighbour returns to x along the opposite direction -- touches only the
-// ~10 % of fluid nodes next to a wall; the wave collects those nodes into a
-// dense list in LDS, evaluates their returned populations one node per lane,
-// and scatters the sums back (compaction instead of per-lane masking of all
-// 18-26 directions).
+// fluid nodes next to a wall (about 12 % of them at porosity 0.7).  A static
+// per-row list of those nodes is built once at set-up; for each plane the
+// wave evaluates the listed nodes one per lane and passes the sums through
+// LDS to the lanes that own them (instead of masking all 18-26 directions of
+// every node).
 //
 // After plane z has received everything it is finalised with one reciprocal
 // of the density (the division-saving form of the paper) and stored; solid
@@ -46,12 +47,11 @@ namespace tau1 {
 
 constexpr int kZrWaves = 4;                 // waves per workgroup
 constexpr int kZrThreads = 64 * kZrWaves;
-constexpr int kZrMaxPX = 9;  // nodes per lane (C * K)
-constexpr int kZrMaxC = 3;
 
 // Tile shapes the autotuner chooses among: z-segment length per work item
-// (tile % 4) and the load schedule (tile >= 4: the three source rows of a
-// plane are loaded together; otherwise one row at a time).
+// (tile % 4) and the load schedule (tile >= 4: rolling prefetch, each source
+// row is requested one row ahead of its use, across planes; otherwise each
+// row is loaded just before it is used).
 constexpr int kNumTiles = 8;
 constexpr int kTileLZ[4] = {16, 32, 64, 128};
 inline int tile_lz(int tile) { return kTileLZ[tile & 3]; }
@@ -124,9 +124,8 @@ __device__ __forceinline__ uint32_t xmask_window(const uint32_t* __restrict__ xm
 // Buffer access.  Each state array and the extended mask get a raw buffer
 // resource; a row's start is the uniform (scalar) offset and a lane's chunk
 // the per-lane offset, so no per-lane address arithmetic is needed.  A lane
-// that has nothing to read or write in a chunk uses an offset beyond the
-// buffer's range: such loads return zeros and such stores are dropped by the
-// hardware range check, without touching memory.
+// with nothing to read (an unused wall-list slot) uses an offset beyond the
+// buffer's range: such loads return zeros without touching memory.
 // ---------------------------------------------------------------------------
 using rsrc_t = __amdgpu_buffer_rsrc_t;
 constexpr int kOob = 0x7ff00000;  // voffset beyond every buffer (< 2 GiB checked on the host)
@@ -318,59 +317,31 @@ __device__ __forceinline__ void push_row(Planes<C * K>& pl, const Src (&s)[C * K
     }
 }
 
-// Bounce-back sums of one fluid node (one per worker lane): every direction k
-// whose neighbour x + c_k is solid returns the node's own equilibrium in k
-// along -c_k.  win[dy+1][dz+1] holds the solid bits around the node (bit 1 =
-// the node itself).  Sums are kept per weight class and weighted at the end.
+// Bounce-back sums of one wall node (one per worker lane): every direction k
+// whose neighbour x + c_k is solid (bit k - 1 of `links`) returns the node's
+// own equilibrium in k along -c_k.  Sums are kept per weight class and
+// weighted at the end.
 template <int Q, int KD = 1>
-__device__ __forceinline__ void bounce_sum(const Src& s, const uint32_t (&win)[3][3],
-                                           float (&d)[3], float (&j)[3][3]) {
+__device__ __forceinline__ void bounce_sum(const Src& s, uint32_t links, float (&d)[3],
+                                           float (&j)[3][3]) {
     if constexpr (KD < Q) {
         using L = Lattice<Q>;
         constexpr int CX = L::c[KD].x, CY = L::c[KD].y, CZ = L::c[KD].z;
         constexpr int cls = (CX != 0) + (CY != 0) + (CZ != 0) - 1;  // face, edge, corner
         // all-ones when the neighbour x + c_k is solid
-        const uint32_t m = (uint32_t)__builtin_amdgcn_sbfe((int)win[CY + 1][CZ + 1], 1 + CX, 1);
+        const uint32_t m = (uint32_t)__builtin_amdgcn_sbfe((int)links, KD - 1, 1);
         const float u = __builtin_bit_cast(float, __builtin_bit_cast(uint32_t, feq_m<CX, CY, CZ>(s)) & m);
         d[cls] += u;
         if constexpr (CX != 0) j[cls][0] -= CX * u;
         if constexpr (CY != 0) j[cls][1] -= CY * u;
         if constexpr (CZ != 0) j[cls][2] -= CZ * u;
-        bounce_sum<Q, KD + 1>(s, win, d, j);
-    }
-}
-
-// Solid-neighbour bits (one per node of a chunk) from the chunk's nine row
-// windows.
-template <int Q, int KD = 1>
-__device__ __forceinline__ uint32_t neighbour_solid(const uint32_t (&win)[3][3]) {
-    if constexpr (KD < Q) {
-        using L = Lattice<Q>;
-        constexpr int CX = L::c[KD].x, CY = L::c[KD].y, CZ = L::c[KD].z;
-        return (win[CY + 1][CZ + 1] >> (1 + CX)) | neighbour_solid<Q, KD + 1>(win);
-    } else {
-        return 0u;
+        bounce_sum<Q, KD + 1>(s, links, d, j);
     }
 }
 
 __device__ __forceinline__ int wrapi(int a, int n) {
     a = a < 0 ? a + n : a;
     return a >= n ? a - n : a;
-}
-
-// position of the n-th (0-based) set bit of m (n < popcount(m))
-__device__ __forceinline__ int nth_set_bit(uint64_t m, int n) {
-    int pos = 0;
-#pragma unroll
-    for (int width = 32; width >= 1; width >>= 1) {
-        const uint64_t part = (m >> pos) & ((1ull << width) - 1);
-        const int c = __builtin_popcountll(part);
-        if (n >= c) {
-            n -= c;
-            pos += width;
-        }
-    }
-    return pos;
 }
 
 __device__ __forceinline__ int64_t uniform64(int64_t v) {
@@ -385,59 +356,53 @@ struct ZrItem {
     static constexpr int Lg = 64 / G;
     static constexpr int PX = C * K;
     static constexpr int ES = (int)sizeof(typename Storage<P>::S);
-    rsrc_t pre[4], post[4], xm;
+    rsrc_t pre[4], post[4], xm, wl;
     int lane, gl;
     bool first_lane, last_lane, active;
     int nx, ny, nz, xw, z0, z1;
-    int yc, ym, yp;
+    int y0, yc, ym, yp;
     int voff[C];   // byte offset of the lane's chunk c inside a row
     int woff[C];   // byte offset of the lane's mask window word, chunk c
     float isr, isu, sr, su, gx, gy, gz;
-    float* lds_state;
-    uint32_t* lds_win;
+    const uint32_t* woffs;  // wall-list row offsets
+    float* lds_res;         // bounce-back sums [4][G * nx] of this wave
 };
 
-// Nine row windows (rows y-1..y+1 x planes z-1..z+1) around plane zc.
+// Solid-bit window of the wave's own row in plane zc, one per chunk: bit b
+// is the node chunk_start + b - 1.
 template <int P, int G, int C, int K>
 __device__ __forceinline__ void load_windows(const ZrItem<P, G, C, K>& it, int zc,
-                                             uint32_t (&win)[C][3][3]) {
-    const int zrow[3] = {wrapi(zc - 1, it.nz), zc, wrapi(zc + 1, it.nz)};
-    const int yrow[3] = {it.ym, it.yc, it.yp};
+                                             uint32_t (&win)[C]) {
+    const int roff = (zc * it.ny + it.yc) * it.xw * 4;
 #pragma unroll
-    for (int dy = 0; dy < 3; ++dy)
-#pragma unroll
-        for (int dz = 0; dz < 3; ++dz) {
-            const int roff = (zrow[dz] * it.ny + yrow[dy]) * it.xw * 4;
-#pragma unroll
-            for (int c = 0; c < C; ++c) {
-                const auto v = G == 1 ? __builtin_amdgcn_raw_buffer_load_b64(it.xm, it.woff[c], roff, 0)
-                                      : __builtin_amdgcn_raw_buffer_load_b64(it.xm, it.woff[c] + roff, 0, 0);
-                const uint64_t u = ((uint64_t)v[1] << 32) | v[0];
-                win[c][dy][dz] = (uint32_t)(u >> ((c * (64 / G) * K + it.gl * K) & 31));
-            }
-        }
+    for (int c = 0; c < C; ++c) {
+        const auto v = G == 1 ? __builtin_amdgcn_raw_buffer_load_b64(it.xm, it.woff[c], roff, 0)
+                              : __builtin_amdgcn_raw_buffer_load_b64(it.xm, it.woff[c] + roff, 0, 0);
+        const uint64_t u = ((uint64_t)v[1] << 32) | v[0];
+        win[c] = (uint32_t)(u >> ((c * (64 / G) * K + it.gl * K) & 31));
+    }
 }
 
+// Fluid flags of the lane's C * K nodes (bit c * K + j).
 template <int C, int K>
-__device__ __forceinline__ uint32_t fluid_bits(const uint32_t (&win)[C][3][3], int dy) {
+__device__ __forceinline__ uint32_t fluid_bits(const uint32_t (&win)[C]) {
     constexpr uint32_t mK = (1u << K) - 1u;
     uint32_t f = 0;
 #pragma unroll
-    for (int c = 0; c < C; ++c) f |= (~(win[c][dy][1] >> 1) & mK) << (c * K);
+    for (int c = 0; c < C; ++c) f |= (~(win[c] >> 1) & mK) << (c * K);
     return f;
 }
 
-// One source row's state (C chunks of K nodes), chunks without fluid read as
-// zeros at no memory cost.
+// One source row's state (C chunks of K nodes).  Whole chunks are read,
+// solid nodes included (they hold zeros): every cache line is then read
+// whole, which costs less than skipping all-solid chunks line by line.
 template <int P, int G, int C, int K>
-__device__ __forceinline__ void load_row(const ZrItem<P, G, C, K>& it, int row, uint32_t fl,
-                                         RawRow<C * K>& r) {
-    constexpr uint32_t mK = (1u << K) - 1u;
+__device__ __forceinline__ void load_row(const ZrItem<P, G, C, K>& it, int row, RawRow<C * K>& r) {
     const int roff = row * it.nx * ZrItem<P, G, C, K>::ES;
     const int soff = G == 1 ? roff : 0;
 #pragma unroll
     for (int c = 0; c < C; ++c) {
-        const int vo = ((fl >> (c * K)) & mK) ? it.voff[c] + (G == 1 ? 0 : roff) : kOob;
+        const int vo = it.voff[c] + (G == 1 ? 0 : roff);
         float t0[K], t1[K], t2[K], t3[K];
         load_chunk<P, K>(it.pre[0], vo, soff, t0, it.isr);
         load_chunk<P, K>(it.pre[1], vo, soff, t1, it.isu);
@@ -453,88 +418,123 @@ __device__ __forceinline__ void load_row(const ZrItem<P, G, C, K>& it, int row, 
     }
 }
 
+// Wall-list state carried along the march: row offsets of the planes ahead
+// (scalars) and the first 64 entries of the next plane (one per lane), loaded
+// one plane ahead so the bounce-back never waits on memory.
+template <int Q>
+struct WallPipe {
+    using E = typename WallEntry<Q>::type;
+    int cur0, cur1;    // entries [cur0, cur1) of the current plane
+    int next0, next1;  // of the next plane
+    E cur;             // entry cur0 + lane, or 0
+};
+
+template <int P, int G, int C, int K>
+__device__ __forceinline__ void wall_offsets(const ZrItem<P, G, C, K>& it, int plane, int& o0,
+                                             int& o1) {
+    const int zc = wrapi(plane % it.nz, it.nz);
+    const int ng = G < it.ny - it.y0 ? G : it.ny - it.y0;
+    const int r0 = zc * it.ny + it.y0;
+    o0 = __builtin_amdgcn_readfirstlane((int)it.woffs[r0]);
+    o1 = __builtin_amdgcn_readfirstlane((int)it.woffs[r0 + ng]);
+}
+
+template <int Q>
+__device__ __forceinline__ typename WallEntry<Q>::type wall_load(rsrc_t wl, int idx, bool ok) {
+    using E = typename WallEntry<Q>::type;
+    const int vo = ok ? idx * (int)sizeof(E) : kOob;
+    if constexpr (sizeof(E) == 8) {
+        const auto v = __builtin_amdgcn_raw_buffer_load_b64(wl, vo, 0, 0);
+        return ((uint64_t)v[1] << 32) | v[0];
+    } else {
+        return __builtin_amdgcn_raw_buffer_load_b32(wl, vo, 0, 0);
+    }
+}
+
+// One stored value (at voff + soff) widened to FP32.
+template <int P>
+__device__ __forceinline__ float load_one(rsrc_t r, int voff, int soff, float isc) {
+    using St = Storage<P>;
+    using S = typename St::S;
+    S tmp[1];
+    if constexpr (sizeof(S) == 4) {
+        const uint32_t w = __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0);
+        __builtin_memcpy(tmp, &w, 4);
+    } else {
+        const unsigned short w = __builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0);
+        __builtin_memcpy(tmp, &w, 2);
+    }
+    return St::load(tmp, 0, isc);
+}
+
+// Stored state of the node of wall-list entry e (widened to FP32), for the
+// bounce-back worker lane; e's row is the wave's row y0 + (e >> 10 & 3) of
+// plane zc.
 template <int Q, int P, int G, int C, int K>
-__device__ __forceinline__ void bounce_back(const ZrItem<P, G, C, K>& it, Plane<C * K>& pc,
-                                            const uint32_t (&win)[C][3][3], uint32_t fown,
-                                            const RawRow<C * K>& ro) {
+__device__ __forceinline__ void wall_state(const ZrItem<P, G, C, K>& it, typename WallEntry<Q>::type e,
+                                           int zc, bool ok, float (&v)[4]) {
+    constexpr int ES = ZrItem<P, G, C, K>::ES;
+    const int x = (int)(e & 1023u);
+    const int row = zc * it.ny + it.y0;
+    const int n = (int)((e >> 10) & 3u) * it.nx + x;  // node from the first row's start
+    const int vo = ok ? n * ES : kOob;
+    const int so = row * it.nx * ES;
+    v[0] = load_one<P>(it.pre[0], vo, so, it.isr);
+    v[1] = load_one<P>(it.pre[1], vo, so, it.isu);
+    v[2] = load_one<P>(it.pre[2], vo, so, it.isu);
+    v[3] = load_one<P>(it.pre[3], vo, so, it.isu);
+}
+
+// Halfway bounce-back (Eq. 11) at the wall nodes of this wave's rows in the
+// current plane.  Lane i evaluates list entry i: the node's own equilibrium
+// in every direction k whose neighbour x + c_k is solid, returned to the node
+// along -c_k.  The node's state comes from the owners' LDS copy; the sums go
+// through LDS back to the owners, which add them to the plane's partial sums
+// and clear their slots for the next plane.
+template <int Q, int P, int G, int C, int K>
+__device__ __forceinline__ void bounce_list(const ZrItem<P, G, C, K>& it, Plane<C * K>& pc,
+                                            const WallPipe<Q>& wp, int zc, const float (&v0)[4]) {
     constexpr int PX = C * K;
     constexpr int Lg = 64 / G;
-    uint32_t nb = 0;
-#pragma unroll
-    for (int c = 0; c < C; ++c) nb |= (neighbour_solid<Q>(win[c]) & ((1u << K) - 1u)) << (c * K);
-    const uint32_t bmask = it.active ? (fown & nb) : 0u;
-    uint64_t bal[PX];
-    int total = 0;
-#pragma unroll
-    for (int j = 0; j < PX; ++j) {
-        bal[j] = __ballot((bmask >> j) & 1u);
-        total += __builtin_popcountll(bal[j]);
-    }
-    if (!total) return;
-    const int lane = it.lane;
-    if (bmask) {
-#pragma unroll
-        for (int j = 0; j < PX; ++j) {
-            it.lds_state[(0 * PX + j) * 64 + lane] = ro.d[j];
-            it.lds_state[(1 * PX + j) * 64 + lane] = ro.vx[j];
-            it.lds_state[(2 * PX + j) * 64 + lane] = ro.vy[j];
-            it.lds_state[(3 * PX + j) * 64 + lane] = ro.vz[j];
-        }
-#pragma unroll
-        for (int c = 0; c < C; ++c)
-#pragma unroll
-            for (int dy = 0; dy < 3; ++dy)
-#pragma unroll
-                for (int dz = 0; dz < 3; ++dz)
-                    it.lds_win[((c * 3 + dy) * 3 + dz) * 64 + lane] = win[c][dy][dz];
-    }
-    __builtin_amdgcn_wave_barrier();
+    constexpr int RS = 64 * PX;  // = G * nx
+    const int total = wp.cur1 - wp.cur0;
+    float* res = it.lds_res;
     for (int base = 0; base < total; base += 64) {
-        const int i = base + lane;
+        const int i = base + it.lane;
+        typename WallEntry<Q>::type e = wp.cur;
+        float v[4] = {v0[0], v0[1], v0[2], v0[3]};
+        if (base > 0) {
+            e = wall_load<Q>(it.wl, wp.cur0 + i, i < total);
+            wall_state<Q>(it, e, zc, i < total, v);
+        }
         if (i < total) {
-            // entry i in slot-major order -> (slot, owner lane)
-            int slot = 0, rank = i, cum = 0;
-            uint64_t m = bal[0];
-#pragma unroll
-            for (int j = 0; j < PX; ++j) {
-                const int cnt = __builtin_popcountll(bal[j]);
-                if (i >= cum && i < cum + cnt) {
-                    slot = j;
-                    rank = i - cum;
-                    m = bal[j];
-                }
-                cum += cnt;
-            }
-            const int owner = nth_set_bit(m, rank);
-            const int ch = slot / K, jj = slot - (slot / K) * K;
-            uint32_t w2[3][3];
-#pragma unroll
-            for (int dy = 0; dy < 3; ++dy)
-#pragma unroll
-                for (int dz = 0; dz < 3; ++dz)
-                    w2[dy][dz] = it.lds_win[((ch * 3 + dy) * 3 + dz) * 64 + owner] >> jj;
-            float* e = it.lds_state + slot * 64 + owner;
-            const Src sw = make_src(e[0], e[PX * 64], e[2 * PX * 64], e[3 * PX * 64]);
-            float d[3] = {0.f, 0.f, 0.f};
-            float jv[3][3] = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};
-            bounce_sum<Q>(sw, w2, d, jv);
+            const int n = (int)((e >> 10) & 3u) * it.nx + (int)(e & 1023u);
+            const uint32_t links = (uint32_t)(e >> 12);
+            const Src sw = make_src(v[0], v[1], v[2], v[3]);
+            float sd[3] = {0.f, 0.f, 0.f};
+            float sj[3][3] = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};
+            bounce_sum<Q>(sw, links, sd, sj);
             constexpr float wf = (float)Lattice<Q>::w_face, we = (float)Lattice<Q>::w_edge,
                             wc = (float)Lattice<Q>::w_corner;
-            e[0] = wf * d[0] + we * d[1] + wc * d[2];
+            res[n] = wf * sd[0] + we * sd[1] + wc * sd[2];
 #pragma unroll
-            for (int a = 0; a < 3; ++a) e[(1 + a) * PX * 64] = wf * jv[0][a] + we * jv[1][a] + wc * jv[2][a];
+            for (int a = 0; a < 3; ++a) res[(1 + a) * RS + n] = wf * sj[0][a] + we * sj[1][a] + wc * sj[2][a];
         }
     }
     __builtin_amdgcn_wave_barrier();
-    if (bmask) {
+    const int grp = G == 1 ? 0 : it.lane / Lg;
 #pragma unroll
-        for (int j = 0; j < PX; ++j) {
-            if ((bmask >> j) & 1u) {
+    for (int comp = 0; comp < 4; ++comp)
 #pragma unroll
-                for (int c = 0; c < 4; ++c) pc.v[c][j] += it.lds_state[(c * PX + j) * 64 + lane];
-            }
+        for (int c = 0; c < C; ++c) {
+            float* e = res + comp * RS + grp * (C * Lg * K) + c * Lg * K + it.gl * K;
+            float t[K];
+            __builtin_memcpy(t, e, sizeof t);
+#pragma unroll
+            for (int j = 0; j < K; ++j) pc.v[comp][c * K + j] += t[j];
+            const float z[K] = {};
+            __builtin_memcpy(e, z, sizeof z);
         }
-    }
     __builtin_amdgcn_wave_barrier();
 }
 
@@ -542,51 +542,53 @@ __device__ __forceinline__ void bounce_back(const ZrItem<P, G, C, K>& it, Plane<
 // zs+1 (pl.p zero on entry).  Finalises and stores plane zs-1 at the end.
 template <int Q, int P, int G, int C, int K, bool HOIST>
 __device__ __forceinline__ void zr_step(const ZrItem<P, G, C, K>& it, int zs, Planes<C * K> pl,
-                                        uint32_t (&win_next)[C][3][3], uint32_t& fluid_prev) {
+                                        uint32_t (&win_next)[C], uint32_t& fluid_prev,
+                                        WallPipe<Q>& wp, RawRow<C * K>& rm) {
     constexpr int PX = C * K;
-    constexpr int Lg = 64 / G;
-    constexpr uint32_t mK = (1u << K) - 1u;
     const int z0 = it.z0, z1 = it.z1, ny = it.ny, nz = it.nz;
     const int zmask = ((zs - 1 >= z0 && zs - 1 < z1) ? 1 : 0) |
                       ((zs >= z0 && zs < z1) ? 2 : 0) |
                       ((zs + 1 >= z0 && zs + 1 < z1) ? 4 : 0);
     const int zc = wrapi(zs % nz, nz);
-    uint32_t win[C][3][3];
-#pragma unroll
-    for (int c = 0; c < C; ++c)
-#pragma unroll
-        for (int dy = 0; dy < 3; ++dy)
-#pragma unroll
-            for (int dz = 0; dz < 3; ++dz) win[c][dy][dz] = win_next[c][dy][dz];
-
-    const uint32_t flm = fluid_bits<C, K>(win, 0);
-    const uint32_t flp = fluid_bits<C, K>(win, 2);
-    const uint32_t fown = fluid_bits<C, K>(win, 1);
+    const uint32_t fown = fluid_bits<C, K>(win_next);
     const int rm_ = zc * ny + it.ym, rp_ = zc * ny + it.yp, ro_ = zc * ny + it.yc;
-    RawRow<PX> rm, rp, ro;
-    if constexpr (HOIST) {
-        load_row(it, rm_, flm, rm);
-        load_row(it, rp_, flp, rp);
-        load_row(it, ro_, fown, ro);
-    }
-    if (zs < z1) load_windows(it, wrapi((zs + 1) % nz, nz), win_next);
+    RawRow<PX> rp, ro;
+    // next plane's windows (also after the segment's last plane: a periodic,
+    // in-range read; unconditional so that no load count depends on a branch)
+    load_windows(it, wrapi((zs + 1) % nz, nz), win_next);
+    // wall list one plane ahead: entries of plane zs + 1, offsets of zs + 2
+    const auto e_next = wall_load<Q>(it.wl, wp.next0 + it.lane, it.lane < wp.next1 - wp.next0);
+    int nn0, nn1;
+    wall_offsets(it, zs + 2, nn0, nn1);
+    // state of this plane's first 64 wall nodes, used by the bounce-back below
+    float wv[4];
+    wall_state<Q>(it, wp.cur, zc, (zmask & 2) && it.lane < wp.cur1 - wp.cur0, wv);
+    // HOIST: rolling prefetch, one source row in flight ahead of its use (row
+    // y-1 of this plane arrived during the previous step); otherwise each row
+    // is loaded just before it is used.
+    if constexpr (HOIST) load_row(it, rp_, rp);
+    else load_row(it, rm_, rm);
 
     // ---- neighbour rows: y-1 sends its c_y = +1 directions, y+1 its c_y = -1
     {
-        if constexpr (!HOIST) load_row(it, rm_, flm, rm);
         Src s[PX];
 #pragma unroll
         for (int j = 0; j < PX; ++j) s[j] = make_src(rm.d[j], rm.vx[j], rm.vy[j], rm.vz[j]);
         push_row<Q, 1, G, C, K>(pl, s, zmask, it.first_lane, it.last_lane);
     }
+    if constexpr (HOIST) load_row(it, ro_, ro);
+    else load_row(it, rp_, rp);
     {
-        if constexpr (!HOIST) load_row(it, rp_, flp, rp);
         Src s[PX];
 #pragma unroll
         for (int j = 0; j < PX; ++j) s[j] = make_src(rp.d[j], rp.vx[j], rp.vy[j], rp.vz[j]);
         push_row<Q, -1, G, C, K>(pl, s, zmask, it.first_lane, it.last_lane);
     }
-    if constexpr (!HOIST) load_row(it, ro_, fown, ro);
+    if constexpr (HOIST) {
+        load_row(it, wrapi((zs + 1) % nz, nz) * ny + it.ym, rm);
+    } else {
+        load_row(it, ro_, ro);
+    }
     // ---- own row: c_y = 0 directions and the rest population
     {
         Src s[PX];
@@ -599,11 +601,16 @@ __device__ __forceinline__ void zr_step(const ZrItem<P, G, C, K>& it, int zs, Pl
             for (int j = 0; j < PX; ++j) pl.c.v[0][j] = __builtin_fmaf(w0, s[j].a, pl.c.v[0][j]);
         }
     }
-    // ---- halfway bounce-back of this plane's wall nodes, compacted per wave
-    if (zmask & 2) bounce_back<Q, P, G, C, K>(it, pl.c, win, fown, ro);
+    // ---- halfway bounce-back at this plane's wall nodes (static list)
+    if (zmask & 2) bounce_list<Q, P, G, C, K>(it, pl.c, wp, zc, wv);
+    wp.cur0 = wp.next0;
+    wp.cur1 = wp.next1;
+    wp.cur = e_next;
+    wp.next0 = nn0;
+    wp.next1 = nn1;
 
-    // ---- plane zs - 1 is complete: finalise and store whole chunks (solid
-    // slots rewrite their zeros); chunks without fluid are dropped
+    // ---- plane zs - 1 is complete: finalise and store whole chunks, solid
+    // slots included (they rewrite their zeros), so every line is written whole
     if ((zmask & 1) && it.active) {
         const int ro2 = (wrapi(zc - 1, nz) * ny + it.yc) * it.nx * ZrItem<P, G, C, K>::ES;
         const int so = G == 1 ? ro2 : 0;
@@ -621,7 +628,7 @@ __device__ __forceinline__ void zr_step(const ZrItem<P, G, C, K>& it, int zs, Pl
                 oy[j] = f ? __builtin_fmaf(pl.m.v[2][sl], r, it.gy) : 0.0f;
                 oz[j] = f ? __builtin_fmaf(pl.m.v[3][sl], r, it.gz) : 0.0f;
             }
-            const int vo = ((fluid_prev >> (c * K)) & mK) ? it.voff[c] + (G == 1 ? 0 : ro2) : kOob;
+            const int vo = it.voff[c] + (G == 1 ? 0 : ro2);
             store_chunk<P, K>(it.post[0], vo, so, od, it.sr);
             store_chunk<P, K>(it.post[1], vo, so, ox, it.su);
             store_chunk<P, K>(it.post[2], vo, so, oy, it.su);
@@ -665,6 +672,7 @@ __device__ __forceinline__ void zr_item(const StepArgs& a, const SampleDev* sd, 
     it.z0 = z0; it.z1 = z1;
     const int y = rg * G + grp;
     it.active = y < it.ny;
+    it.y0 = rg * G;
     it.yc = it.active ? y : it.ny - 1;
     it.ym = wrapi(it.yc - 1, it.ny);
     it.yp = wrapi(it.yc + 1, it.ny);
@@ -689,25 +697,34 @@ __device__ __forceinline__ void zr_item(const StepArgs& a, const SampleDev* sd, 
     it.isr = inv_scale_rho<P>(a); it.isu = inv_scale_u<P>(a);
     it.sr = scale_rho<P>(a); it.su = scale_u<P>(a);
     it.gx = 2.0f * a.ghf[0]; it.gy = 2.0f * a.ghf[1]; it.gz = 2.0f * a.ghf[2];
-    it.lds_state = lds;
-    it.lds_win = reinterpret_cast<uint32_t*>(lds + 4 * PX * 64);
+    it.woffs = reinterpret_cast<const uint32_t*>(a.base + uniform64(sd->wall_off));
+    it.wl = make_rsrc(a.base + uniform64(sd->wall_list),
+                      (uint32_t)(uniform64(sd->n) * (int64_t)sizeof(typename WallEntry<Q>::type)));
+    it.lds_res = lds;
 
     Plane<PX> A, B, Cp;
     zero_plane(A);
     zero_plane(B);
     zero_plane(Cp);
     uint32_t fluid_prev = 0;
-    uint32_t win_next[C][3][3];
+    uint32_t win_next[C];
     load_windows(it, wrapi((z0 - 1) % it.nz, it.nz), win_next);
+    WallPipe<Q> wp;
+    wp.cur0 = wp.cur1 = 0;
+    wp.cur = 0;
+    wall_offsets(it, z0, wp.next0, wp.next1);
+    RawRow<PX> rm;  // row y-1 of the first source plane (rolling prefetch)
+    if constexpr (HOIST)
+        load_row(it, wrapi((z0 - 1) % it.nz, it.nz) * it.ny + it.ym, rm);
     int zs = z0 - 1;
     while (true) {
-        zr_step<Q, P, G, C, K, HOIST>(it, zs, Planes<PX>{A, B, Cp}, win_next, fluid_prev);
+        zr_step<Q, P, G, C, K, HOIST>(it, zs, Planes<PX>{A, B, Cp}, win_next, fluid_prev, wp, rm);
         zero_plane(A);
         if (++zs > z1) break;
-        zr_step<Q, P, G, C, K, HOIST>(it, zs, Planes<PX>{B, Cp, A}, win_next, fluid_prev);
+        zr_step<Q, P, G, C, K, HOIST>(it, zs, Planes<PX>{B, Cp, A}, win_next, fluid_prev, wp, rm);
         zero_plane(B);
         if (++zs > z1) break;
-        zr_step<Q, P, G, C, K, HOIST>(it, zs, Planes<PX>{Cp, A, B}, win_next, fluid_prev);
+        zr_step<Q, P, G, C, K, HOIST>(it, zs, Planes<PX>{Cp, A, B}, win_next, fluid_prev, wp, rm);
         zero_plane(Cp);
         if (++zs > z1) break;
     }
@@ -715,13 +732,24 @@ __device__ __forceinline__ void zr_item(const StepArgs& a, const SampleDev* sd, 
 
 // Work item (4 x int32): sample, row group, z-segment start, z-segment end.
 // Workgroups are remapped so that each XCD walks a contiguous range of items
-// (neighbouring rows share their y-1 / y+1 reads in that XCD's L2).  V >= 0
-// compiles one lane layout only (its register budget alone sets occupancy);
-// V = -1 switches per item, for batches of differently sized samples.
+// (neighbouring rows share their y-1 / y+1 reads in that XCD's L2).  Each
+// instance compiles one lane layout V (its register budget alone sets the
+// occupancy); batches of differently sized samples launch one instance per
+// layout present.
 template <int Q, int P, int V, bool HOIST>
 __global__ __launch_bounds__(kZrThreads) void k_zmarch(StepArgs a) {
-    __shared__ float lds_all[kZrWaves][(4 * kZrMaxPX + 9 * kZrMaxC) * 64];
+    static_assert(V >= 0 && V < kNumVariants, "one lane layout per instance");
+    constexpr int G = kVariants[V].g, C = kVariants[V].c, K = kVariants[V].k;
+    constexpr int kPX = C * K;
+    // per wave: bounce-back sums [4][64 * kPX]
+    __shared__ float lds_all[kZrWaves][4 * kPX * 64];
     const int wave = threadIdx.x >> 6;
+    {
+        // bounce-back sums start at zero; every use clears what it read
+        float* l = lds_all[wave];
+        for (int i = __lane_id(); i < 4 * kPX * 64; i += 64) l[i] = 0.0f;
+        __builtin_amdgcn_wave_barrier();
+    }
     const int nwg = gridDim.x;
     const int b = blockIdx.x;
     // XCD-aware order: dispatch is round-robin over 8 XCDs
@@ -736,31 +764,7 @@ __global__ __launch_bounds__(kZrThreads) void k_zmarch(StepArgs a) {
         const int4 tv = reinterpret_cast<const int4*>(a.tiles)[item];
         const int4 t = make_int4(__builtin_amdgcn_readfirstlane(tv.x), __builtin_amdgcn_readfirstlane(tv.y),
                                  __builtin_amdgcn_readfirstlane(tv.z), __builtin_amdgcn_readfirstlane(tv.w));
-        const SampleDev* sd = a.samples + t.x;
-        float* lds = lds_all[wave];
-#define TAU1_ZR_CASE(VV, GG, CC, KK)                                          \
-    if constexpr (V == VV || V < 0) {                                         \
-        if (V >= 0 || __builtin_amdgcn_readfirstlane(sd->variant) == VV) {    \
-            zr_item<Q, P, GG, CC, KK, HOIST>(a, sd, t.y, t.z, t.w, lds);     \
-            continue;                                                         \
-        }                                                                     \
-    }
-        TAU1_ZR_CASE(0, 1, 1, 1)
-        TAU1_ZR_CASE(1, 1, 1, 2)
-        TAU1_ZR_CASE(2, 1, 1, 3)
-        TAU1_ZR_CASE(3, 1, 1, 4)
-        TAU1_ZR_CASE(4, 1, 1, 5)
-        TAU1_ZR_CASE(5, 1, 2, 3)
-        TAU1_ZR_CASE(6, 1, 2, 4)
-        TAU1_ZR_CASE(7, 2, 1, 1)
-        TAU1_ZR_CASE(8, 2, 1, 3)
-        TAU1_ZR_CASE(9, 2, 1, 5)
-        TAU1_ZR_CASE(10, 2, 1, 7)
-        TAU1_ZR_CASE(11, 2, 3, 3)
-        TAU1_ZR_CASE(12, 4, 1, 1)
-        TAU1_ZR_CASE(13, 4, 1, 3)
-        TAU1_ZR_CASE(14, 4, 1, 5)
-#undef TAU1_ZR_CASE
+        zr_item<Q, P, G, C, K, HOIST>(a, a.samples + t.x, t.y, t.z, t.w, lds_all[wave]);
     }
 }
 
@@ -800,15 +804,6 @@ inline void* pick_zmarch(int q, int p, int variant, bool hoist) {
     return nullptr;
 }
 
-// Lane layout shared by every sample of a context, or -1 when they differ.
-template <typename SH>
-inline int common_variant(const SH* s, int n) {
-    int v = n > 0 ? s[0].dev.variant : -1;
-    for (int i = 1; i < n; ++i)
-        if (s[i].dev.variant != v) return -1;
-    return v;
-}
-
 inline int zmarch_threads(int) { return kZrThreads; }
 
 // Resident-sized grid: at most enough workgroups for every item, rounded to
@@ -823,7 +818,7 @@ inline int64_t zmarch_grid(int64_t nitems, int) {
 // Supported when every sample has a lane layout and each state array and
 // mask fits the 32-bit buffer offsets below the out-of-range offset.
 template <typename SH>
-inline bool zmarch_supported(int, int prec, const SH* s, int n) {
+inline bool zmarch_supported(int q, int prec, const SH* s, int n) {
     if (!zmarch_precision_ok(prec)) return false;
     const int64_t es = storage_bytes(prec);
     for (int i = 0; i < n; ++i) {
@@ -831,6 +826,7 @@ inline bool zmarch_supported(int, int prec, const SH* s, int n) {
         if (sd.variant < 0) return false;
         if (sd.stride * es + 65536 > (int64_t)kOob) return false;
         if (((int64_t)sd.xwords * sd.ny * sd.nz + 2) * 4 + 65536 > (int64_t)kOob) return false;
+        if (sd.n * (q > 19 ? 8 : 4) + 65536 > (int64_t)kOob) return false;  // wall list
     }
     return true;
 }
@@ -842,14 +838,15 @@ inline void zmarch_tiling(SampleDev& sd) {
     sd.tiles_y = (sd.ny + g - 1) / g;
 }
 
-// Work list for z-segment length lz: items (sample, row group, z0, z1) with
-// row groups fastest so neighbouring rows are neighbouring items.
+// Work list of the samples with lane layout `variant`, for z-segment length
+// lz: items (sample, row group, z0, z1) with row groups fastest so
+// neighbouring rows are neighbouring items.
 template <typename SH>
-inline std::vector<int32_t> zmarch_worklist(const SH* s, int n, int lz) {
+inline std::vector<int32_t> zmarch_worklist(const SH* s, int n, int lz, int variant) {
     std::vector<int32_t> out;
     for (int i = 0; i < n; ++i) {
         const SampleDev& sd = s[i].dev;
-        if (sd.variant < 0) continue;
+        if (sd.variant < 0 || sd.variant != variant) continue;
         for (int z0 = 0; z0 < sd.nz; z0 += lz) {
             const int z1 = z0 + lz < sd.nz ? z0 + lz : sd.nz;
             for (int rg = 0; rg < sd.tiles_y; ++rg) {

@@ -17,7 +17,7 @@ namespace tau1 {
 
 void* TAU1_CAT(zm_kernel_, TAU1_Q, TAU1_P)(int variant, bool hoist) {
 #define TAU1_K(V, H) reinterpret_cast<void*>(&k_zmarch<TAU1_Q, TAU1_P, V, H>)
-    if (variant < 0) return TAU1_K(-1, false);
+    if (variant < 0) return nullptr;
     switch (variant) {
 #define TAU1_V(V) case V: return hoist ? TAU1_K(V, true) : TAU1_K(V, false);
         TAU1_V(0) TAU1_V(1) TAU1_V(2) TAU1_V(3) TAU1_V(4) TAU1_V(5) TAU1_V(6) TAU1_V(7)
