@@ -143,3 +143,66 @@ def test_porous_against_oracle_f32():
     mref, kref = oracle.reduce(ref, 0, g[0])
     assert abs(k - kref) <= 1e-5 * abs(kref)
     sim.close()
+
+
+def test_prefetch_tiles_bitwise_identical():
+    """Rolling-prefetch tiles (4-7) form every sum in the same order as 0-3."""
+    geo = inputs.spheres(64, 20, 70, 5.0, 0.7, seed=12)
+    g = (1e-5, 0, 0)
+    outs = []
+    for tile in (0, 4, 5, 6, 7):
+        print(f"[case] tile {tile}", flush=True)
+        sim, out = run_gpu([(geo.solid,)], 19, "f32", g, 9, kernel=1, tile=tile)
+        outs.append(out[0])
+        sim.close()
+    for o in outs[1:]:
+        assert o[0].tobytes() == outs[0][0].tobytes()
+        assert o[1].tobytes() == outs[0][1].tobytes()
+
+
+def test_graph_replays_match_single_launches():
+    """A two-layout batch (two independent graph chains) replayed several
+    times, with readback between replays, against single launches."""
+    samples = [inputs.spheres(64, 20, 12, 4.0, 0.7, seed=5).solid,
+               inputs.spheres(96, 10, 14, 5.0, 0.6, seed=6).solid]
+    g = (1e-4, 2e-5, 0)
+    print("[case] graph replays, two layouts", flush=True)
+    a = tau1.Sim([tau1.Sample(s) for s in samples], lattice=19, precision="f32", g=g,
+                 graph_chunk=2, kernel=1)
+    b = tau1.Sim([tau1.Sample(s) for s in samples], lattice=19, precision="f32", g=g,
+                 graph_chunk=1000, kernel=1)
+    for r in range(5):
+        a.step(2)
+        b.step(2)
+        for i in range(2):
+            da, ua = a.moments(i)
+            db, ub = b.moments(i)
+            assert da.tobytes() == db.tobytes(), (r, i)
+            assert ua.tobytes() == ub.tobytes(), (r, i)
+    a.close()
+    b.close()
+
+
+def test_autotune_keeps_state_and_uses_cache(tmp_path):
+    geo = inputs.spheres(64, 32, 40, 4.0, 0.7, seed=8)
+    cache = str(tmp_path / "tau1_tune.txt")
+    g = (1e-5, 0, 0)
+    print("[case] autotune", flush=True)
+    sim = tau1.Sim([tau1.Sample(geo.solid)], lattice=19, precision="f32", g=g, tune_cache=cache)
+    sim.step(3)
+    before = sim.moments(0)
+    tuned = sim.autotune(2)["tile"]
+    after = sim.moments(0)
+    assert before[0].tobytes() == after[0].tobytes()
+    assert before[1].tobytes() == after[1].tobytes()
+    sim.step(2)
+    ref = run_oracle(19, geo.solid, None, None, g, 5)
+    err = reduced_errors(sim.moments(0), ref, geo.solid)
+    assert err["u_rel_l2"] <= 8.0 * 2.0 ** -24
+    sim.close()
+    with open(cache) as f:
+        assert any(line.startswith("tau1 gfx950 q19 p1 ") for line in f)
+    again = tau1.Sim([tau1.Sample(geo.solid)], lattice=19, precision="f32", g=g,
+                     tune_cache=cache)
+    assert again.info()["tile"] == tuned
+    again.close()
