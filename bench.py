@@ -83,7 +83,7 @@ def kernel_source_hash() -> str:
 
 
 def read_counters():
-    """HBM bytes per launch recorded by rocprofv3 for the main kernel, or None."""
+    """HBM bytes per launch (per tile) recorded by rocprofv3 for the main kernel."""
     if not os.path.exists(COUNTERS):
         return None
     vals = {}
@@ -360,9 +360,9 @@ def main(argv=None):
         geo = geos["main"]
         traffic = None
         cnt = read_counters()
-        if (cnt and cnt.get("source_sha256") == kernel_source_hash()
-                and int(cnt.get("tile", -99)) == main_res["tile"]):
-            traffic = float(cnt["hbm_bytes_per_launch"])
+        key = f"hbm_bytes_per_launch_tile{main_res['tile']}"
+        if cnt and cnt.get("source_sha256") == kernel_source_hash() and key in cnt:
+            traffic = float(cnt[key])
         line.update({
             "value": main_res["gflups"], "unit": "GFLUPS",
             "ms_per_step": main_res["ms_per_step"],
