@@ -467,7 +467,7 @@ tau1_status set_tile(tau1_ctx* ctx, int tile) {
     for (int v : layouts) {
         const int64_t item0 = (int64_t)tl.size() / 4;
         std::vector<int32_t> part =
-            zmarch_worklist(ctx->plan.s.data(), ctx->nsamples, tile_lz(tile), v);
+            zmarch_worklist(ctx->plan.s.data(), ctx->nsamples, tile_lz(tile), v, tile_hoist(tile));
         tl.insert(tl.end(), part.begin(), part.end());
         tau1_ctx::ZGroup g;
         g.variant = v;

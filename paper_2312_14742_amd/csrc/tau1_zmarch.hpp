@@ -55,9 +55,9 @@ constexpr int kZrWaves = 4;                 // waves per workgroup
 constexpr int kZrThreads = 64 * kZrWaves;
 
 // Tile shapes the autotuner chooses among: z-segment length per work item
-// (tile % 4) and the load schedule (tile >= 4: rolling prefetch, each source
-// row is requested one row ahead of its use, across planes; otherwise each
-// row is loaded just before it is used).
+// (tile % 4) and the load schedule (tile >= 4: rows shared through LDS inside
+// the workgroup for one-row-per-wave layouts, rolling prefetch for the
+// others; otherwise each source row is loaded just before it is used).
 constexpr int kNumTiles = 8;
 constexpr int kTileLZ[4] = {16, 32, 64, 128};
 inline int tile_lz(int tile) { return kTileLZ[tile & 3]; }
@@ -385,6 +385,12 @@ struct ZrItem {
     float isr, isu, sr, su, gx, gy, gz;
     const uint32_t* woffs;  // wall-list row offsets
     float* lds_res;         // bounce-back sums [4][G * nx] of this wave
+    // shared-row mode (one row per wave): the workgroup's row slots
+    // [2 planes][kZrWaves waves][4 components][nx], this wave's index, and
+    // whether rows y-1 / y+1 are the rows of the neighbouring waves
+    float* lds_rows;
+    int wave;
+    bool share_m, share_p;
 };
 
 // Solid-bit window of the wave's own row in plane zc, one per chunk: bit b
@@ -434,6 +440,36 @@ __device__ __forceinline__ void load_row(const ZrItem<P, G, C, K>& it, int row, 
             r.vy[c * K + j] = t2[j];
             r.vz[c * K + j] = t3[j];
         }
+    }
+}
+
+// A lane's chunks of one row in an LDS slot [4 components][nx] (one row per
+// wave): write the wave's own row, or read a neighbouring wave's.
+template <int P, int G, int C, int K>
+__device__ __forceinline__ void row_to_lds(const ZrItem<P, G, C, K>& it, float* slot,
+                                           const RawRow<C * K>& r) {
+    constexpr int RS = 64 * C * K;
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        float* e = slot + c * 64 * K + it.gl * K;
+        __builtin_memcpy(e, &r.d[c * K], 4 * K);
+        __builtin_memcpy(e + RS, &r.vx[c * K], 4 * K);
+        __builtin_memcpy(e + 2 * RS, &r.vy[c * K], 4 * K);
+        __builtin_memcpy(e + 3 * RS, &r.vz[c * K], 4 * K);
+    }
+}
+
+template <int P, int G, int C, int K>
+__device__ __forceinline__ void row_from_lds(const ZrItem<P, G, C, K>& it, const float* slot,
+                                             RawRow<C * K>& r) {
+    constexpr int RS = 64 * C * K;
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        const float* e = slot + c * 64 * K + it.gl * K;
+        __builtin_memcpy(&r.d[c * K], e, 4 * K);
+        __builtin_memcpy(&r.vx[c * K], e + RS, 4 * K);
+        __builtin_memcpy(&r.vy[c * K], e + 2 * RS, 4 * K);
+        __builtin_memcpy(&r.vz[c * K], e + 3 * RS, 4 * K);
     }
 }
 
@@ -510,25 +546,49 @@ __device__ __forceinline__ void wall_state(const ZrItem<P, G, C, K>& it, typenam
 // along -c_k.  The node's state comes from the owners' LDS copy; the sums go
 // through LDS back to the owners, which add them to the plane's partial sums
 // and clear their slots for the next plane.
+//
+// Shared-row mode (state != nullptr): the node's state comes from the wave's
+// own row slot in LDS, and the sums go through `res`, a slot the owners clear
+// first.  Otherwise the state of the first 64 nodes is v0 (loaded at the
+// start of the step), later ones are loaded here, and `res` is the wave's
+// sum area, which the owners clear after reading.
 template <int Q, int P, int G, int C, int K>
 __device__ __forceinline__ void bounce_list(const ZrItem<P, G, C, K>& it, Plane<C * K>& pc,
-                                            const WallPipe<Q>& wp, int zc, const float (&v0)[4]) {
+                                            const WallPipe<Q>& wp, int zc, const float (&v0)[4],
+                                            const float* state, float* res) {
     constexpr int PX = C * K;
     constexpr int Lg = 64 / G;
     constexpr int RS = 64 * PX;  // = G * nx
     const int total = wp.cur1 - wp.cur0;
-    float* res = it.lds_res;
+    const int grp = G == 1 ? 0 : it.lane / Lg;
+    if (state) {
+#pragma unroll
+        for (int comp = 0; comp < 4; ++comp)
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                const float z[K] = {};
+                __builtin_memcpy(res + comp * RS + grp * (C * Lg * K) + c * Lg * K + it.gl * K, z,
+                                 sizeof z);
+            }
+        __builtin_amdgcn_wave_barrier();
+    }
     for (int base = 0; base < total; base += 64) {
         const int i = base + it.lane;
         typename WallEntry<Q>::type e = wp.cur;
         float v[4] = {v0[0], v0[1], v0[2], v0[3]};
         if (base > 0) {
             e = wall_load<Q>(it.wl, wp.cur0 + i, i < total);
-            wall_state<Q>(it, e, zc, i < total, v);
+            if (!state) wall_state<Q>(it, e, zc, i < total, v);
         }
         if (i < total) {
             const int n = (int)((e >> 10) & 3u) * it.nx + (int)(e & 1023u);
             const uint32_t links = (uint32_t)(e >> 12);
+            if (state) {
+                v[0] = state[n];
+                v[1] = state[RS + n];
+                v[2] = state[2 * RS + n];
+                v[3] = state[3 * RS + n];
+            }
             const Src sw = make_src(v[0], v[1], v[2], v[3]);
             float sd[3] = {0.f, 0.f, 0.f};
             float sj[3][3] = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};
@@ -541,7 +601,6 @@ __device__ __forceinline__ void bounce_list(const ZrItem<P, G, C, K>& it, Plane<
         }
     }
     __builtin_amdgcn_wave_barrier();
-    const int grp = G == 1 ? 0 : it.lane / Lg;
 #pragma unroll
     for (int comp = 0; comp < 4; ++comp)
 #pragma unroll
@@ -551,19 +610,32 @@ __device__ __forceinline__ void bounce_list(const ZrItem<P, G, C, K>& it, Plane<
             __builtin_memcpy(t, e, sizeof t);
 #pragma unroll
             for (int j = 0; j < K; ++j) pc.v[comp][c * K + j] += t[j];
-            const float z[K] = {};
-            __builtin_memcpy(e, z, sizeof z);
+            if (!state) {
+                const float z[K] = {};
+                __builtin_memcpy(e, z, sizeof z);
+            }
         }
     __builtin_amdgcn_wave_barrier();
 }
 
 // One source plane zs: pl.m, pl.c, pl.p are the destination planes zs-1, zs,
-// zs+1 (pl.p zero on entry).  Finalises and stores plane zs-1 at the end.
+// zs+1 (pl.p starts empty).  Finalises and stores plane zs-1 at the end.
+//
+// Load schedules (HOIST = false: each source row loaded just before it is
+// used).  HOIST with one row per wave (G = 1) shares rows inside the
+// workgroup: each wave loads only its own row, publishes it in an LDS slot,
+// and after one workgroup barrier per plane reads rows y-1 / y+1 from its
+// neighbours' slots; only the block's edge rows come from memory.  HOIST with
+// G > 1: rolling prefetch, row y-1 of the next plane (`ahead`) is requested
+// during this plane.
 template <int Q, int P, int G, int C, int K, bool HOIST>
 __device__ __forceinline__ void zr_step(const ZrItem<P, G, C, K>& it, int zs, Planes<C * K> pl,
                                         uint32_t (&win_next)[C], uint32_t& fluid_prev,
-                                        WallPipe<Q>& wp, RawRow<C * K>& rm) {
+                                        WallPipe<Q>& wp, RawRow<C * K>& ahead) {
     constexpr int PX = C * K;
+    constexpr bool SHARE = HOIST && G == 1;
+    constexpr bool ROLL = HOIST && G != 1;
+    constexpr int RS = 64 * PX;
     const int z0 = it.z0, z1 = it.z1, ny = it.ny, nz = it.nz;
     const int zmask = ((zs - 1 >= z0 && zs - 1 < z1) ? 1 : 0) |
                       ((zs >= z0 && zs < z1) ? 2 : 0) |
@@ -571,7 +643,7 @@ __device__ __forceinline__ void zr_step(const ZrItem<P, G, C, K>& it, int zs, Pl
     const int zc = wrapi(zs % nz, nz);
     const uint32_t fown = fluid_bits<C, K>(win_next);
     const int rm_ = zc * ny + it.ym, rp_ = zc * ny + it.yp, ro_ = zc * ny + it.yc;
-    RawRow<PX> rp, ro;
+    RawRow<PX> rm, rp, ro;
     // next plane's windows (also after the segment's last plane: a periodic,
     // in-range read; unconditional so that no load count depends on a branch)
     load_windows(it, wrapi((zs + 1) % nz, nz), win_next);
@@ -580,13 +652,30 @@ __device__ __forceinline__ void zr_step(const ZrItem<P, G, C, K>& it, int zs, Pl
     int nn0, nn1;
     wall_offsets(it, zs + 2, nn0, nn1);
     // state of this plane's first 64 wall nodes, used by the bounce-back below
-    float wv[4];
-    wall_state<Q>(it, wp.cur, zc, (zmask & 2) && it.lane < wp.cur1 - wp.cur0, wv);
-    // HOIST: rolling prefetch, one source row in flight ahead of its use (row
-    // y-1 of this plane arrived during the previous step); otherwise each row
-    // is loaded just before it is used.
-    if constexpr (HOIST) load_row(it, rp_, rp);
-    else load_row(it, rm_, rm);
+    float wv[4] = {0.f, 0.f, 0.f, 0.f};
+    if constexpr (!SHARE)
+        wall_state<Q>(it, wp.cur, zc, (zmask & 2) && it.lane < wp.cur1 - wp.cur0, wv);
+
+    float* own = nullptr;
+    float* spare = nullptr;
+    if constexpr (SHARE) {
+        // slots of this plane (parity of zs) and of the next one
+        const int b = zs & 1;
+        own = it.lds_rows + (b * kZrWaves + it.wave) * 4 * RS;
+        spare = it.lds_rows + ((b ^ 1) * kZrWaves + it.wave) * 4 * RS;
+        load_row(it, ro_, ro);
+        if (!it.share_m) load_row(it, rm_, rm);
+        if (!it.share_p) load_row(it, rp_, rp);
+        row_to_lds(it, own, ro);
+        __syncthreads();
+        if (it.share_m) row_from_lds(it, it.lds_rows + (b * kZrWaves + it.wave - 1) * 4 * RS, rm);
+        if (it.share_p) row_from_lds(it, it.lds_rows + (b * kZrWaves + it.wave + 1) * 4 * RS, rp);
+    } else if constexpr (ROLL) {
+        rm = ahead;
+        load_row(it, rp_, rp);
+    } else {
+        load_row(it, rm_, rm);
+    }
 
     // ---- neighbour rows: y-1 sends its c_y = +1 directions, y+1 its c_y = -1
     {
@@ -595,19 +684,16 @@ __device__ __forceinline__ void zr_step(const ZrItem<P, G, C, K>& it, int zs, Pl
         for (int j = 0; j < PX; ++j) s[j] = make_src(rm.d[j], rm.vx[j], rm.vy[j], rm.vz[j]);
         push_row<Q, 1, G, C, K>(pl, s, zmask, it.first_lane, it.last_lane);
     }
-    if constexpr (HOIST) load_row(it, ro_, ro);
-    else load_row(it, rp_, rp);
+    if constexpr (ROLL) load_row(it, ro_, ro);
+    else if constexpr (!SHARE) load_row(it, rp_, rp);
     {
         Src s[PX];
 #pragma unroll
         for (int j = 0; j < PX; ++j) s[j] = make_src(rp.d[j], rp.vx[j], rp.vy[j], rp.vz[j]);
         push_row<Q, -1, G, C, K>(pl, s, zmask, it.first_lane, it.last_lane);
     }
-    if constexpr (HOIST) {
-        load_row(it, wrapi((zs + 1) % nz, nz) * ny + it.ym, rm);
-    } else {
-        load_row(it, ro_, ro);
-    }
+    if constexpr (ROLL) load_row(it, wrapi((zs + 1) % nz, nz) * ny + it.ym, ahead);
+    else if constexpr (!SHARE) load_row(it, ro_, ro);
     // ---- own row: c_y = 0 directions and the rest population
     {
         Src s[PX];
@@ -621,7 +707,9 @@ __device__ __forceinline__ void zr_step(const ZrItem<P, G, C, K>& it, int zs, Pl
         }
     }
     // ---- halfway bounce-back at this plane's wall nodes (static list)
-    if (zmask & 2) bounce_list<Q, P, G, C, K>(it, pl.c, wp, zc, wv);
+    if (zmask & 2)
+        bounce_list<Q, P, G, C, K>(it, pl.c, wp, zc, wv, SHARE ? own : nullptr,
+                                   SHARE ? spare : it.lds_res);
     wp.cur0 = wp.next0;
     wp.cur1 = wp.next1;
     wp.cur = e_next;
@@ -672,7 +760,8 @@ __device__ __forceinline__ void zero_plane(Plane<PX>& q) {
 // value is marked wave-uniform, so per-item quantities live in scalar registers.
 template <int Q, int P, int G, int C, int K, bool HOIST>
 __device__ __forceinline__ void zr_item(const StepArgs& a, const SampleDev* sd, int rg, int z0,
-                                        int z1, float* __restrict__ lds) {
+                                        int z1, float* __restrict__ lds, int wave,
+                                        float* __restrict__ lds_rows) {
     using St = Storage<P>;
     using S = typename St::S;
     using It = ZrItem<P, G, C, K>;
@@ -720,6 +809,12 @@ __device__ __forceinline__ void zr_item(const StepArgs& a, const SampleDev* sd, 
     it.wl = make_rsrc(a.base + uniform64(sd->wall_list),
                       (uint32_t)(uniform64(sd->n) * (int64_t)sizeof(typename WallEntry<Q>::type)));
     it.lds_res = lds;
+    it.lds_rows = lds_rows;
+    it.wave = wave;
+    // rows y -/+ 1 are the neighbouring waves' rows: the block's waves hold
+    // consecutive rows, and a row past ny wraps to a row outside the block
+    it.share_m = wave > 0;
+    it.share_p = wave < kZrWaves - 1 && y + 1 < it.ny;
 
     Plane<PX> A, B, Cp;
     zero_plane(A);
@@ -732,8 +827,9 @@ __device__ __forceinline__ void zr_item(const StepArgs& a, const SampleDev* sd, 
     wp.cur0 = wp.cur1 = 0;
     wp.cur = 0;
     wall_offsets(it, z0, wp.next0, wp.next1);
-    RawRow<PX> rm;  // row y-1 of the first source plane (rolling prefetch)
-    if constexpr (HOIST)
+    // row y-1 of the first source plane, requested ahead (rolling prefetch)
+    RawRow<PX> rm;
+    if constexpr (HOIST && G != 1)
         load_row(it, wrapi((z0 - 1) % it.nz, it.nz) * it.ny + it.ym, rm);
     int zs = z0 - 1;
     while (true) {
@@ -760,13 +856,16 @@ __global__ __launch_bounds__(kZrThreads) void k_zmarch(StepArgs a) {
     static_assert(V >= 0 && V < kNumVariants, "one lane layout per instance");
     constexpr int G = kVariants[V].g, C = kVariants[V].c, K = kVariants[V].k;
     constexpr int kPX = C * K;
-    // per wave: bounce-back sums [4][64 * kPX]
-    __shared__ float lds_all[kZrWaves][4 * kPX * 64];
+    constexpr bool kShare = HOIST && G == 1;
+    // shared rows: [2 planes][kZrWaves][4][64 * kPX] (the bounce-back sums use
+    // the other plane's slot); otherwise bounce-back sums [kZrWaves][4][64 * kPX]
+    constexpr int kLds = (kShare ? 2 : 1) * kZrWaves * 4 * kPX * 64;
+    __shared__ float lds_all[kLds];
     const int wave = threadIdx.x >> 6;
-    {
+    float* lds_wave = lds_all + wave * 4 * kPX * 64;
+    if constexpr (!kShare) {
         // bounce-back sums start at zero; every use clears what it read
-        float* l = lds_all[wave];
-        for (int i = __lane_id(); i < 4 * kPX * 64; i += 64) l[i] = 0.0f;
+        for (int i = __lane_id(); i < 4 * kPX * 64; i += 64) lds_wave[i] = 0.0f;
         __builtin_amdgcn_wave_barrier();
     }
     const int nwg = gridDim.x;
@@ -783,7 +882,7 @@ __global__ __launch_bounds__(kZrThreads) void k_zmarch(StepArgs a) {
         const int4 tv = reinterpret_cast<const int4*>(a.tiles)[item];
         const int4 t = make_int4(__builtin_amdgcn_readfirstlane(tv.x), __builtin_amdgcn_readfirstlane(tv.y),
                                  __builtin_amdgcn_readfirstlane(tv.z), __builtin_amdgcn_readfirstlane(tv.w));
-        zr_item<Q, P, G, C, K, HOIST>(a, a.samples + t.x, t.y, t.z, t.w, lds_all[wave]);
+        zr_item<Q, P, G, C, K, HOIST>(a, a.samples + t.x, t.y, t.z, t.w, lds_wave, wave, lds_all);
     }
 }
 
@@ -857,18 +956,29 @@ inline void zmarch_tiling(SampleDev& sd) {
     sd.tiles_y = (sd.ny + g - 1) / g;
 }
 
+// Row groups of a sample in the work list: with shared rows (one row per
+// wave, `blocks`), padded to whole blocks of kZrWaves rows, so that the waves
+// of a workgroup always hold one block of consecutive rows with the same
+// z-segment (the extra rows are inactive: they store nothing).
+inline int zmarch_rows(const SampleDev& sd, bool blocks) {
+    if (blocks && sd.variant >= 0 && kVariants[sd.variant].g == 1)
+        return (sd.tiles_y + kZrWaves - 1) / kZrWaves * kZrWaves;
+    return sd.tiles_y;
+}
+
 // Work list of the samples with lane layout `variant`, for z-segment length
 // lz: items (sample, row group, z0, z1) with row groups fastest so
 // neighbouring rows are neighbouring items.
 template <typename SH>
-inline std::vector<int32_t> zmarch_worklist(const SH* s, int n, int lz, int variant) {
+inline std::vector<int32_t> zmarch_worklist(const SH* s, int n, int lz, int variant, bool blocks) {
     std::vector<int32_t> out;
     for (int i = 0; i < n; ++i) {
         const SampleDev& sd = s[i].dev;
         if (sd.variant < 0 || sd.variant != variant) continue;
+        const int rows = zmarch_rows(sd, blocks);
         for (int z0 = 0; z0 < sd.nz; z0 += lz) {
             const int z1 = z0 + lz < sd.nz ? z0 + lz : sd.nz;
-            for (int rg = 0; rg < sd.tiles_y; ++rg) {
+            for (int rg = 0; rg < rows; ++rg) {
                 out.push_back(i);
                 out.push_back(rg);
                 out.push_back(z0);
@@ -885,7 +995,7 @@ inline int64_t zmarch_max_items(const SH* s, int n) {
     for (int i = 0; i < n; ++i) {
         const SampleDev& sd = s[i].dev;
         if (sd.variant < 0) continue;
-        items += (int64_t)sd.tiles_y * ((sd.nz + tile_lz(0) - 1) / tile_lz(0));
+        items += (int64_t)zmarch_rows(sd, true) * ((sd.nz + tile_lz(0) - 1) / tile_lz(0));
     }
     return items;
 }

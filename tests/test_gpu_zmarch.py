@@ -39,14 +39,17 @@ LAYOUT_DIMS = [
 ]
 
 
+@pytest.mark.parametrize("tile", [2, 6])
 @pytest.mark.parametrize("dims", LAYOUT_DIMS)
 @pytest.mark.parametrize("q", [15, 19, 27])
-def test_layouts_f32(q, dims):
+def test_layouts_f32(q, dims, tile):
+    """Tile 2 loads each source row itself; tile 6 shares rows through LDS
+    (one-row layouts) or prefetches them (multi-row layouts)."""
     nx, ny, nz = dims
     solid, drho, u = inputs.random_state(nx, ny, nz, seed=5000 + nx + 3 * ny + 7 * nz)
     g = (1e-5, -2e-5, 3e-6)
-    print(f"[case] zmarch f32 q={q} dims={dims}", flush=True)
-    sim, out = run_gpu([(solid, drho, u)], q, "f32", g, 6, kernel=1)
+    print(f"[case] zmarch f32 q={q} dims={dims} tile={tile}", flush=True)
+    sim, out = run_gpu([(solid, drho, u)], q, "f32", g, 6, kernel=1, tile=tile)
     assert sim.info()["kernel"] == 1
     ref = run_oracle(q, solid, drho, u, g, 6)
     err = reduced_errors(out[0], ref, solid)
@@ -72,14 +75,17 @@ def test_layouts_16bit(prec, dims):
     sim.close()
 
 
-@pytest.mark.parametrize("dims", [(64, 1, 1), (32, 1, 3), (16, 2, 1), (64, 3, 2), (32, 5, 1)])
-def test_degenerate_periodic(dims):
-    """ny or nz of 1-3: the stencil wraps onto the node's own row/plane."""
+@pytest.mark.parametrize("tile", [2, 6])
+@pytest.mark.parametrize("dims", [(64, 1, 1), (32, 1, 3), (16, 2, 1), (64, 3, 2), (32, 5, 1),
+                                  (64, 5, 3), (128, 6, 2), (64, 9, 4)])
+def test_degenerate_periodic(dims, tile):
+    """ny or nz of 1-3 (the stencil wraps onto the node's own row/plane) and
+    ny not a multiple of the four rows a workgroup shares."""
     nx, ny, nz = dims
     solid, drho, u = inputs.random_state(nx, ny, nz, seed=77 + nx * ny * nz)
     g = (1e-5, 3e-6, -2e-6)
-    print(f"[case] zmarch degenerate dims={dims}", flush=True)
-    sim, out = run_gpu([(solid, drho, u)], 19, "f32", g, 5, kernel=1)
+    print(f"[case] zmarch degenerate dims={dims} tile={tile}", flush=True)
+    sim, out = run_gpu([(solid, drho, u)], 19, "f32", g, 5, kernel=1, tile=tile)
     ref = run_oracle(19, solid, drho, u, g, 5)
     err = reduced_errors(out[0], ref, solid)
     for key, b in bounds("f32", np.abs(u).max()).items():
