@@ -623,9 +623,10 @@ __device__ __forceinline__ void bounce_list(const ZrItem<P, G, C, K>& it, Plane<
 //
 // Load schedules (HOIST = false: each source row loaded just before it is
 // used).  HOIST with one row per wave (G = 1) shares rows inside the
-// workgroup: each wave loads only its own row, publishes it in an LDS slot,
-// and after one workgroup barrier per plane reads rows y-1 / y+1 from its
-// neighbours' slots; only the block's edge rows come from memory.  HOIST with
+// workgroup: each wave loads only its own row (requested at the end of the
+// previous plane, `ahead`), publishes it in an LDS slot, and after one
+// workgroup barrier per plane reads rows y-1 / y+1 from its neighbours'
+// slots; only the block's edge rows come from memory.  HOIST with
 // G > 1: rolling prefetch, row y-1 of the next plane (`ahead`) is requested
 // during this plane.
 template <int Q, int P, int G, int C, int K, bool HOIST>
@@ -663,7 +664,7 @@ __device__ __forceinline__ void zr_step(const ZrItem<P, G, C, K>& it, int zs, Pl
         const int b = zs & 1;
         own = it.lds_rows + (b * kZrWaves + it.wave) * 4 * RS;
         spare = it.lds_rows + ((b ^ 1) * kZrWaves + it.wave) * 4 * RS;
-        load_row(it, ro_, ro);
+        ro = ahead;
         if (!it.share_m) load_row(it, rm_, rm);
         if (!it.share_p) load_row(it, rp_, rp);
         row_to_lds(it, own, ro);
@@ -743,6 +744,9 @@ __device__ __forceinline__ void zr_step(const ZrItem<P, G, C, K>& it, int zs, Pl
         }
     }
     fluid_prev = fown;
+    // shared rows: the next plane's own row, requested once this plane's
+    // registers are free (it lands while the next step starts)
+    if constexpr (SHARE) load_row(it, wrapi((zs + 1) % nz, nz) * ny + it.yc, ahead);
 }
 
 template <int PX>
@@ -827,10 +831,11 @@ __device__ __forceinline__ void zr_item(const StepArgs& a, const SampleDev* sd, 
     wp.cur0 = wp.cur1 = 0;
     wp.cur = 0;
     wall_offsets(it, z0, wp.next0, wp.next1);
-    // row y-1 of the first source plane, requested ahead (rolling prefetch)
+    // row requested ahead for the first source plane: the own row (shared
+    // rows) or row y-1 (rolling prefetch)
     RawRow<PX> rm;
-    if constexpr (HOIST && G != 1)
-        load_row(it, wrapi((z0 - 1) % it.nz, it.nz) * it.ny + it.ym, rm);
+    if constexpr (HOIST)
+        load_row(it, wrapi((z0 - 1) % it.nz, it.nz) * it.ny + (G == 1 ? it.yc : it.ym), rm);
     int zs = z0 - 1;
     while (true) {
         zr_step<Q, P, G, C, K, HOIST>(it, zs, Planes<PX>{A, B, Cp}, win_next, fluid_prev, wp, rm);
