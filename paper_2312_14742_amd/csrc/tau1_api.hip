@@ -214,7 +214,7 @@ Launch step_launch(const tau1_ctx* ctx, int kernel, int tile, int g) {
     Launch l{};
     if (kernel == 1) {
         const auto& grp = ctx->zgroups[g];
-        l.fn = pick_zmarch(ctx->lattice, ctx->precision, grp.variant, tile_hoist(tile));
+        l.fn = pick_zmarch(ctx->lattice, ctx->precision, grp.variant, tile_mode(tile));
         l.block = dim3(zmarch_threads(tile));
         l.grid = dim3((unsigned)zmarch_grid(grp.args[0].ntiles, tile));
         l.shmem = 0;
@@ -467,7 +467,8 @@ tau1_status set_tile(tau1_ctx* ctx, int tile) {
     for (int v : layouts) {
         const int64_t item0 = (int64_t)tl.size() / 4;
         std::vector<int32_t> part =
-            zmarch_worklist(ctx->plan.s.data(), ctx->nsamples, tile_lz(tile), v, tile_hoist(tile));
+            zmarch_worklist(ctx->plan.s.data(), ctx->nsamples, tile_lz(tile), v,
+                            zr_share(kVariants[v].g, tile_mode(tile)));
         tl.insert(tl.end(), part.begin(), part.end());
         tau1_ctx::ZGroup g;
         g.variant = v;

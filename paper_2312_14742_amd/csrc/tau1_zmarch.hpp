@@ -55,13 +55,20 @@ constexpr int kZrWaves = 4;                 // waves per workgroup
 constexpr int kZrThreads = 64 * kZrWaves;
 
 // Tile shapes the autotuner chooses among: z-segment length per work item
-// (tile % 4) and the load schedule (tile >= 4: rows shared through LDS inside
-// the workgroup for one-row-per-wave layouts, rolling prefetch for the
-// others; otherwise each source row is loaded just before it is used).
-constexpr int kNumTiles = 8;
+// (tile % 4) and the load schedule, tile / 4:
+//   0  each source row is loaded just before it is used;
+//   1  rows shared through LDS inside the workgroup (one-row-per-wave
+//      layouts; rolling prefetch for the others);
+//   2  rolling prefetch: row y-1 of the next plane is requested during this
+//      plane.
+constexpr int kNumTiles = 12;
 constexpr int kTileLZ[4] = {16, 32, 64, 128};
 inline int tile_lz(int tile) { return kTileLZ[tile & 3]; }
-inline bool tile_hoist(int tile) { return tile >= 4; }
+inline int tile_mode(int tile) { return tile / 4; }
+
+// Load schedule of a (layout, mode) pair: shared rows need one row per wave.
+constexpr bool zr_share(int g, int mode) { return mode == 1 && g == 1; }
+constexpr bool zr_roll(int g, int mode) { return mode == 2 || (mode == 1 && g != 1); }
 
 // Lane layouts (G, C, K) compiled into the kernel; nx = C * (64 / G) * K.
 struct ZrVariant {
@@ -621,21 +628,21 @@ __device__ __forceinline__ void bounce_list(const ZrItem<P, G, C, K>& it, Plane<
 // One source plane zs: pl.m, pl.c, pl.p are the destination planes zs-1, zs,
 // zs+1 (pl.p starts empty).  Finalises and stores plane zs-1 at the end.
 //
-// Load schedules (HOIST = false: each source row loaded just before it is
-// used).  HOIST with one row per wave (G = 1) shares rows inside the
-// workgroup: each wave loads only its own row (requested at the end of the
-// previous plane, `ahead`), publishes it in an LDS slot, and after one
-// workgroup barrier per plane reads rows y-1 / y+1 from its neighbours'
-// slots; only the block's edge rows come from memory.  HOIST with
-// G > 1: rolling prefetch, row y-1 of the next plane (`ahead`) is requested
-// during this plane.
-template <int Q, int P, int G, int C, int K, bool HOIST>
+// Load schedules (MODE, the tile's mode).  Mode 0: each source row is
+// loaded just before it is used.  Shared rows (mode 1, one row per wave):
+// each wave loads only its own row (requested at the end of the previous
+// plane, `ahead`), publishes it in an LDS slot, and after one workgroup
+// barrier per plane reads rows y-1 / y+1 from its neighbours' slots; only the
+// block's edge rows come from memory.  Rolling prefetch (mode 2, and mode 1
+// with G > 1): row y-1 of the next plane (`ahead`) is requested during this
+// plane.
+template <int Q, int P, int G, int C, int K, int MODE>
 __device__ __forceinline__ void zr_step(const ZrItem<P, G, C, K>& it, int zs, Planes<C * K> pl,
                                         uint32_t (&win_next)[C], uint32_t& fluid_prev,
                                         WallPipe<Q>& wp, RawRow<C * K>& ahead) {
     constexpr int PX = C * K;
-    constexpr bool SHARE = HOIST && G == 1;
-    constexpr bool ROLL = HOIST && G != 1;
+    constexpr bool SHARE = zr_share(G, MODE);
+    constexpr bool ROLL = zr_roll(G, MODE);
     constexpr int RS = 64 * PX;
     const int z0 = it.z0, z1 = it.z1, ny = it.ny, nz = it.nz;
     const int zmask = ((zs - 1 >= z0 && zs - 1 < z1) ? 1 : 0) |
@@ -762,7 +769,7 @@ __device__ __forceinline__ void zero_plane(Plane<PX>& q) {
 // unrolled by three), so no partial sums are copied between planes.
 // The sample descriptor is read field by field with its own types and every
 // value is marked wave-uniform, so per-item quantities live in scalar registers.
-template <int Q, int P, int G, int C, int K, bool HOIST>
+template <int Q, int P, int G, int C, int K, int MODE>
 __device__ __forceinline__ void zr_item(const StepArgs& a, const SampleDev* sd, int rg, int z0,
                                         int z1, float* __restrict__ lds, int wave,
                                         float* __restrict__ lds_rows) {
@@ -834,17 +841,17 @@ __device__ __forceinline__ void zr_item(const StepArgs& a, const SampleDev* sd, 
     // row requested ahead for the first source plane: the own row (shared
     // rows) or row y-1 (rolling prefetch)
     RawRow<PX> rm;
-    if constexpr (HOIST)
-        load_row(it, wrapi((z0 - 1) % it.nz, it.nz) * it.ny + (G == 1 ? it.yc : it.ym), rm);
+    if constexpr (MODE != 0)
+        load_row(it, wrapi((z0 - 1) % it.nz, it.nz) * it.ny + (zr_share(G, MODE) ? it.yc : it.ym), rm);
     int zs = z0 - 1;
     while (true) {
-        zr_step<Q, P, G, C, K, HOIST>(it, zs, Planes<PX>{A, B, Cp}, win_next, fluid_prev, wp, rm);
+        zr_step<Q, P, G, C, K, MODE>(it, zs, Planes<PX>{A, B, Cp}, win_next, fluid_prev, wp, rm);
         zero_plane(A);
         if (++zs > z1) break;
-        zr_step<Q, P, G, C, K, HOIST>(it, zs, Planes<PX>{B, Cp, A}, win_next, fluid_prev, wp, rm);
+        zr_step<Q, P, G, C, K, MODE>(it, zs, Planes<PX>{B, Cp, A}, win_next, fluid_prev, wp, rm);
         zero_plane(B);
         if (++zs > z1) break;
-        zr_step<Q, P, G, C, K, HOIST>(it, zs, Planes<PX>{Cp, A, B}, win_next, fluid_prev, wp, rm);
+        zr_step<Q, P, G, C, K, MODE>(it, zs, Planes<PX>{Cp, A, B}, win_next, fluid_prev, wp, rm);
         zero_plane(Cp);
         if (++zs > z1) break;
     }
@@ -856,12 +863,12 @@ __device__ __forceinline__ void zr_item(const StepArgs& a, const SampleDev* sd, 
 // instance compiles one lane layout V (its register budget alone sets the
 // occupancy); batches of differently sized samples launch one instance per
 // layout present.
-template <int Q, int P, int V, bool HOIST>
+template <int Q, int P, int V, int MODE>
 __global__ __launch_bounds__(kZrThreads) void k_zmarch(StepArgs a) {
     static_assert(V >= 0 && V < kNumVariants, "one lane layout per instance");
     constexpr int G = kVariants[V].g, C = kVariants[V].c, K = kVariants[V].k;
     constexpr int kPX = C * K;
-    constexpr bool kShare = HOIST && G == 1;
+    constexpr bool kShare = zr_share(G, MODE);
     // shared rows: [2 planes][kZrWaves][4][64 * kPX] (the bounce-back sums use
     // the other plane's slot); otherwise bounce-back sums [kZrWaves][4][64 * kPX]
     constexpr int kLds = (kShare ? 2 : 1) * kZrWaves * 4 * kPX * 64;
@@ -887,13 +894,13 @@ __global__ __launch_bounds__(kZrThreads) void k_zmarch(StepArgs a) {
         const int4 tv = reinterpret_cast<const int4*>(a.tiles)[item];
         const int4 t = make_int4(__builtin_amdgcn_readfirstlane(tv.x), __builtin_amdgcn_readfirstlane(tv.y),
                                  __builtin_amdgcn_readfirstlane(tv.z), __builtin_amdgcn_readfirstlane(tv.w));
-        zr_item<Q, P, G, C, K, HOIST>(a, a.samples + t.x, t.y, t.z, t.w, lds_wave, wave, lds_all);
+        zr_item<Q, P, G, C, K, MODE>(a, a.samples + t.x, t.y, t.z, t.w, lds_wave, wave, lds_all);
     }
 }
 
 // Kernel table of one (lattice, precision) pair; defined in the per-pair
 // translation units built from tau1_zmarch_inst.hip.
-#define TAU1_ZM_TABLE_DECL(QQ, PP) void* zm_kernel_##QQ##_##PP(int variant, bool hoist);
+#define TAU1_ZM_TABLE_DECL(QQ, PP) void* zm_kernel_##QQ##_##PP(int variant, int mode);
 TAU1_ZM_TABLE_DECL(15, 1) TAU1_ZM_TABLE_DECL(15, 2) TAU1_ZM_TABLE_DECL(15, 3)
 TAU1_ZM_TABLE_DECL(19, 1) TAU1_ZM_TABLE_DECL(19, 2) TAU1_ZM_TABLE_DECL(19, 3)
 TAU1_ZM_TABLE_DECL(27, 1) TAU1_ZM_TABLE_DECL(27, 2) TAU1_ZM_TABLE_DECL(27, 3)
@@ -912,17 +919,17 @@ inline bool zmarch_tile_ok(int, int prec, int tile) {
 
 inline int zmarch_default_tile(int, int) { return 2; }  // z-segments of 64 planes
 
-inline void* pick_zmarch(int q, int p, int variant, bool hoist) {
+inline void* pick_zmarch(int q, int p, int variant, int mode) {
     switch (q * 10 + p) {
-        case 151: return zm_kernel_15_1(variant, hoist);
-        case 152: return zm_kernel_15_2(variant, hoist);
-        case 153: return zm_kernel_15_3(variant, hoist);
-        case 191: return zm_kernel_19_1(variant, hoist);
-        case 192: return zm_kernel_19_2(variant, hoist);
-        case 193: return zm_kernel_19_3(variant, hoist);
-        case 271: return zm_kernel_27_1(variant, hoist);
-        case 272: return zm_kernel_27_2(variant, hoist);
-        case 273: return zm_kernel_27_3(variant, hoist);
+        case 151: return zm_kernel_15_1(variant, mode);
+        case 152: return zm_kernel_15_2(variant, mode);
+        case 153: return zm_kernel_15_3(variant, mode);
+        case 191: return zm_kernel_19_1(variant, mode);
+        case 192: return zm_kernel_19_2(variant, mode);
+        case 193: return zm_kernel_19_3(variant, mode);
+        case 271: return zm_kernel_27_1(variant, mode);
+        case 272: return zm_kernel_27_2(variant, mode);
+        case 273: return zm_kernel_27_3(variant, mode);
     }
     return nullptr;
 }

@@ -15,16 +15,24 @@ namespace tau1 {
 #define TAU1_CAT2(a, b, c) a##b##_##c
 #define TAU1_CAT(a, b, c) TAU1_CAT2(a, b, c)
 
-void* TAU1_CAT(zm_kernel_, TAU1_Q, TAU1_P)(int variant, bool hoist) {
-#define TAU1_K(V, H) reinterpret_cast<void*>(&k_zmarch<TAU1_Q, TAU1_P, V, H>)
-    if (variant < 0) return nullptr;
+// Kernel of layout V for load mode 0-2; mode 1 on a multi-row layout is the
+// same schedule as mode 2 and uses that instance.
+template <int V>
+void* zm_pick(int mode) {
+    if (mode == 0) return reinterpret_cast<void*>(&k_zmarch<TAU1_Q, TAU1_P, V, 0>);
+    if constexpr (kVariants[V].g == 1)
+        if (mode == 1) return reinterpret_cast<void*>(&k_zmarch<TAU1_Q, TAU1_P, V, 1>);
+    return reinterpret_cast<void*>(&k_zmarch<TAU1_Q, TAU1_P, V, 2>);
+}
+
+void* TAU1_CAT(zm_kernel_, TAU1_Q, TAU1_P)(int variant, int mode) {
+    if (mode < 0 || mode > 2) return nullptr;
     switch (variant) {
-#define TAU1_V(V) case V: return hoist ? TAU1_K(V, true) : TAU1_K(V, false);
+#define TAU1_V(V) case V: return zm_pick<V>(mode);
         TAU1_V(0) TAU1_V(1) TAU1_V(2) TAU1_V(3) TAU1_V(4) TAU1_V(5) TAU1_V(6) TAU1_V(7)
         TAU1_V(8) TAU1_V(9) TAU1_V(10) TAU1_V(11) TAU1_V(12) TAU1_V(13) TAU1_V(14)
 #undef TAU1_V
     }
-#undef TAU1_K
     return nullptr;
 }
 

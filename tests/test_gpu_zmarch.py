@@ -39,12 +39,13 @@ LAYOUT_DIMS = [
 ]
 
 
-@pytest.mark.parametrize("tile", [2, 6])
+@pytest.mark.parametrize("tile", [2, 6, 10])
 @pytest.mark.parametrize("dims", LAYOUT_DIMS)
 @pytest.mark.parametrize("q", [15, 19, 27])
 def test_layouts_f32(q, dims, tile):
     """Tile 2 loads each source row itself; tile 6 shares rows through LDS
-    (one-row layouts) or prefetches them (multi-row layouts)."""
+    (one-row layouts) or prefetches them (multi-row layouts); tile 10
+    prefetches them."""
     nx, ny, nz = dims
     solid, drho, u = inputs.random_state(nx, ny, nz, seed=5000 + nx + 3 * ny + 7 * nz)
     g = (1e-5, -2e-5, 3e-6)
@@ -152,11 +153,12 @@ def test_porous_against_oracle_f32():
 
 
 def test_prefetch_tiles_bitwise_identical():
-    """Rolling-prefetch tiles (4-7) form every sum in the same order as 0-3."""
+    """Shared-row (4-7) and rolling-prefetch (8-11) tiles form every sum in
+    the same order as the just-in-time tiles (0-3)."""
     geo = inputs.spheres(64, 20, 70, 5.0, 0.7, seed=12)
     g = (1e-5, 0, 0)
     outs = []
-    for tile in (0, 4, 5, 6, 7):
+    for tile in (0, 4, 5, 6, 7, 8, 9, 10, 11):
         print(f"[case] tile {tile}", flush=True)
         sim, out = run_gpu([(geo.solid,)], 19, "f32", g, 9, kernel=1, tile=tile)
         outs.append(out[0])
