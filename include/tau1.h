@@ -33,6 +33,14 @@
  * synchronises (tau1_moments, tau1_permeability, tau1_sync).
  *
  * Threading: a context is not thread-safe; distinct contexts are independent.
+ *
+ * State layout (internal to the workspace; results are bit-for-bit the same
+ * in both): "dense" stores every node; "packed" stores only the runs of K
+ * consecutive x-nodes (the z-march lane chunks, K fixed by nx) that hold at
+ * least one fluid node, so the state is smaller and a step moves fewer bytes.
+ * Packing applies to the samples whose nx has a one-row-per-wave z-march
+ * layout (nx = 64, 128, 192, 256, 320, 384, 512); the other samples of the
+ * context stay dense.
  */
 #ifndef TAU1_H
 #define TAU1_H
@@ -91,10 +99,20 @@ typedef struct {
     size_t workspace_bytes;
     int32_t kernel;         /* step kernel: -1 = automatic (tuned or default),
                                0 = per-node gather, 1 = z-march tiles          */
-    int32_t tile;           /* z-march tile shape index, -1 = automatic        */
+    int32_t tile;           /* z-march tile shape, -1 = automatic; 0-15 =
+                               z-segment of 16/32/64/128 planes (tile % 4) x
+                               load schedule (tile / 4: 0 just in time,
+                               1 rows shared through LDS, 2 rolling prefetch,
+                               3 shared rows on the packed layout); a packed
+                               context takes 12-15, a dense one 0-11          */
     int32_t f16_log2_scale_rho; /* F16 storage: stored = value * 2^s; 0 = 20   */
     int32_t f16_log2_scale_u;   /* F16 storage scale of the velocity; 0 = 20   */
     const char *tune_cache; /* path of the autotune JSON cache, or NULL         */
+    int32_t layout;         /* state layout: -1 = automatic (packed for F32
+                               z-march contexts unless tile is 0-11, dense
+                               otherwise), 0 = dense, 1 = packed
+                               (TAU1_E_UNSUPPORTED if no sample can be
+                               packed: F64, kernel 0, other nx)            */
 } tau1_desc;
 
 /* Static facts about a created context (host copy). */
@@ -103,6 +121,7 @@ typedef struct {
     int32_t kernel;          /* step kernel in use                          */
     int32_t tile;            /* tile shape index in use (z-march)           */
     int32_t graph_chunk;
+    int32_t layout;          /* 1 if any sample is stored packed, else 0    */
     int64_t n_nodes;         /* all samples                                 */
     int64_t n_fluid;         /* all samples                                 */
     int64_t steps_done;

@@ -31,6 +31,7 @@ size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 struct SampleHost {
     SampleDev dev;
     int64_t n_fluid;
+    std::vector<uint32_t> ctab;  // packed layout: chunk table (4 words per entry)
 };
 
 // Byte layout of the workspace for one descriptor.
@@ -43,6 +44,8 @@ struct Plan {
     size_t total = 0;
     int64_t ntiles = 0;
     int64_t total_blocks = 0;
+    bool packed = false;       // some sample uses the packed layout
+    bool pack_refused = false; // packed layout requested but no sample qualifies
     std::vector<SampleHost> s;
 };
 
@@ -56,6 +59,7 @@ tau1_status validate(const tau1_desc* d) {
     if (d->graph_chunk < 0 || (d->graph_chunk % 2) != 0) return TAU1_E_INVALID;
     if (d->kernel < -1 || d->kernel > 1) return TAU1_E_INVALID;
     if (d->tile < -1 || d->tile >= kNumTiles) return TAU1_E_INVALID;
+    if (d->layout < -1 || d->layout > 1) return TAU1_E_INVALID;
     for (int a = 0; a < 3; ++a)
         if (!std::isfinite(d->g[a])) return TAU1_E_INVALID;
     if (d->f16_log2_scale_rho < 0 || d->f16_log2_scale_rho > 40 ||
@@ -71,7 +75,39 @@ tau1_status validate(const tau1_desc* d) {
     return TAU1_OK;
 }
 
-Plan make_plan(const tau1_desc* d) {
+// Packed layout of one sample: its rows are cut into lane chunks of k nodes,
+// `groups` groups of 64 chunks per row.  Returns the number of chunks holding
+// a fluid node; with `tab` it also writes the chunk table (per row and group:
+// fluid bitmap lo, hi, packed index of the group's first fluid chunk, 0).
+int64_t chunk_table(const tau1_sample& in, int k, int groups, uint32_t* tab) {
+    const int64_t rows = in.ny * in.nz;
+    int64_t rank = 0;
+    for (int64_t r = 0; r < rows; ++r) {
+        const uint8_t* row = in.solid + r * in.nx;
+        for (int g = 0; g < groups; ++g) {
+            uint64_t bits = 0;
+            for (int l = 0; l < 64; ++l) {
+                const uint8_t* ch = row + (int64_t)(g * 64 + l) * k;
+                bool fluid = false;
+                for (int j = 0; j < k; ++j) fluid |= ch[j] == 0;
+                bits |= (uint64_t)fluid << l;
+            }
+            if (tab) {
+                uint32_t* e = tab + (r * groups + g) * 4;
+                e[0] = (uint32_t)bits;
+                e[1] = (uint32_t)(bits >> 32);
+                e[2] = (uint32_t)rank;
+                e[3] = 0;
+            }
+            rank += __builtin_popcountll(bits);
+        }
+    }
+    return rank;
+}
+
+// Workspace plan; `tables` also builds the packed layout's chunk tables
+// (the size query only counts chunks).
+Plan make_plan(const tau1_desc* d, bool tables) {
     Plan p;
     const int sz = storage_bytes(d->precision);
     size_t off = 0;
@@ -96,6 +132,26 @@ Plan make_plan(const tau1_desc* d) {
         zmarch_tiling(sd);
         maxn = std::max<int64_t>(maxn, sd.n);
     }
+    // packed layout: by default for FP32 (there the step is bound by memory
+    // traffic) unless a dense-layout tile is asked for, for any z-march
+    // precision on request; one-row-per-wave lane layouts only, and only
+    // where the z-march kernel runs
+    const bool zm = zmarch_supported(d->lattice, d->precision, p.s.data(), d->n_samples);
+    const bool auto_pack = d->precision == kF32 && (d->tile < 0 || tile_mode(d->tile) == 3);
+    const bool pack = zm && d->kernel != 0 && (d->layout == 1 || (d->layout < 0 && auto_pack));
+    for (int i = 0; pack && i < d->n_samples; ++i) {
+        SampleDev& sd = p.s[i].dev;
+        if (kVariants[sd.variant].g != 1) continue;
+        const int k = kVariants[sd.variant].k;
+        const int groups = kVariants[sd.variant].c;
+        if (tables) p.s[i].ctab.assign((size_t)sd.ny * sd.nz * groups * 4, 0u);
+        const int64_t nch = chunk_table(d->samples[i], k, groups,
+                                        tables ? p.s[i].ctab.data() : nullptr);
+        sd.pk = k;
+        sd.stride = (int64_t)(align_up((size_t)std::max<int64_t>(nch * k, 1) * sz, kAlign) / sz);
+        p.packed = true;
+    }
+    p.pack_refused = d->layout == 1 && !p.packed;
     tiles = zmarch_max_items(p.s.data(), d->n_samples);
     p.total_blocks = blocks;
     p.ntiles = tiles;
@@ -113,6 +169,10 @@ Plan make_plan(const tau1_desc* d) {
             off = align_up(off + sizeof(uint32_t) * ((size_t)sd.ny * sd.nz + 1), kAlign);
             sd.wall_list = (int64_t)off;
             off = align_up(off + (d->lattice == 27 ? 8 : 4) * (size_t)sd.n + 8, kAlign);
+        }
+        if (sd.pk) {
+            sd.chunk_tab = (int64_t)off;
+            off = align_up(off + 16 * (size_t)sd.ny * sd.nz * kVariants[sd.variant].c, kAlign);
         }
         for (int b = 0; b < 2; ++b) {
             sd.state[b] = (int64_t)off;
@@ -372,7 +432,13 @@ tau1_status upload_sample_t(tau1_ctx* ctx, int s, const tau1_sample& in) {
         const tau1_status st = build_wall_list(ctx, sd);
         if (st != TAU1_OK) return st;
     }
-    // state
+    if (sd.pk) {
+        const auto& tab = ctx->plan.s[s].ctab;
+        HIP_TRY(hipMemcpyAsync(ctx->base + sd.chunk_tab, tab.data(), sizeof(uint32_t) * tab.size(),
+                               hipMemcpyHostToDevice, ctx->stream));
+        HIP_TRY(hipStreamSynchronize(ctx->stream));
+    }
+    // state (the packed layout's upload kernel skips nodes of all-solid chunks)
     for (int64_t i0 = 0; i0 < n; i0 += chunk) {
         const int64_t len = std::min(chunk, n - i0);
         uint8_t* st_solid = stage;
@@ -525,7 +591,9 @@ tau1_status tau1_workspace_size(const tau1_desc* desc, size_t* bytes) {
     const tau1_status v = validate(desc);
     if (v != TAU1_OK) return v;
     try {
-        *bytes = make_plan(desc).total;
+        const Plan p = make_plan(desc, false);
+        if (p.pack_refused) return TAU1_E_UNSUPPORTED;
+        *bytes = p.total;
     } catch (const std::bad_alloc&) {
         return TAU1_E_NOMEM;
     }
@@ -553,10 +621,21 @@ tau1_status tau1_create(const tau1_desc* desc, tau1_ctx** out) {
     tau1_ctx* ctx = new (std::nothrow) tau1_ctx();
     if (!ctx) return TAU1_E_NOMEM;
     try {
-        ctx->plan = make_plan(desc);
+        ctx->plan = make_plan(desc, true);
     } catch (const std::bad_alloc&) {
         delete ctx;
         return TAU1_E_NOMEM;
+    }
+    if (ctx->plan.pack_refused) {
+        delete ctx;
+        return TAU1_E_UNSUPPORTED;
+    }
+    // an explicit tile must belong to the context's layout
+    if (desc->tile >= 0 && desc->kernel != 0 &&
+        zmarch_supported(desc->lattice, desc->precision, ctx->plan.s.data(), desc->n_samples) &&
+        !zmarch_tile_ok(desc->precision, ctx->plan.packed, desc->tile)) {
+        delete ctx;
+        return TAU1_E_INVALID;
     }
     if (desc->workspace_bytes < ctx->plan.total) {
         delete ctx;
@@ -626,10 +705,11 @@ tau1_status tau1_create(const tau1_desc* desc, tau1_ctx** out) {
         return TAU1_E_UNSUPPORTED;
     }
     ctx->kernel = desc->kernel >= 0 ? desc->kernel : (zm ? 1 : 0);
-    int tile = desc->tile >= 0 ? desc->tile : zmarch_default_tile(ctx->lattice, ctx->precision);
+    const bool packed = ctx->plan.packed;
+    int tile = desc->tile >= 0 ? desc->tile : zmarch_default_tile(packed);
     if (ctx->kernel == 1 && desc->tile < 0 && !ctx->cache.empty()) {
         int t = zmarch_cache_lookup(ctx->cache.c_str(), ctx->lattice, ctx->precision,
-                                    ctx->n_nodes);
+                                    ctx->n_nodes, packed);
         if (t >= 0) tile = t;
     }
     if (zm) {
@@ -726,7 +806,7 @@ tau1_status tau1_autotune(tau1_ctx* ctx, int32_t trial_steps) {
     float best = 1e30f;
     int best_tile = ctx->tile;
     for (int t = 0; t < kNumTiles; ++t) {
-        if (!zmarch_tile_ok(ctx->lattice, ctx->precision, t)) continue;
+        if (!zmarch_tile_ok(ctx->precision, ctx->plan.packed, t)) continue;
         st = set_tile(ctx, t);
         if (st != TAU1_OK) break;
         // the trial reads the current buffer and writes the spare one only
@@ -764,6 +844,7 @@ tau1_status tau1_get_info(const tau1_ctx* ctx, tau1_info* info) {
     info->kernel = ctx->kernel;
     info->tile = ctx->tile;
     info->graph_chunk = ctx->graph_chunk;
+    info->layout = ctx->plan.packed ? 1 : 0;
     info->n_nodes = ctx->n_nodes;
     info->n_fluid = ctx->n_fluid;
     info->steps_done = ctx->steps_done;

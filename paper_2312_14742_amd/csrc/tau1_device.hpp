@@ -121,6 +121,15 @@ inline constexpr int storage_bytes(int prec) {
 // Per-sample descriptor in device memory.  All offsets are byte offsets from
 // the workspace base.  State buffer b (0 or 1) holds four arrays of `stride`
 // elements: drho | vx | vy | vz.
+//
+// Two layouts of those arrays:
+//   dense   element i is node i = x + nx (y + ny z);
+//   packed  the nodes are cut into chunks of pk consecutive x-nodes (the
+//           z-march lane chunks) and only chunks holding at least one fluid
+//           node are stored, in node order; chunk table entry (row, c), rows
+//           r = y + ny z, describes the 64 chunks c * 64 .. c * 64 + 63 of the
+//           row: a 64-bit fluid bitmap (uint32 lo, hi) and the packed index of
+//           its first fluid chunk (uint32), then one unused word.
 // ---------------------------------------------------------------------------
 // Wall-list entry: x (bits 0-9), y mod G (10-11), solid-neighbour bit of
 // direction k at bit 11 + k.
@@ -138,12 +147,13 @@ struct SampleDev {
     int64_t xmask;        // byte offset of the extended (periodic) row mask
     int64_t wall_off;     // byte offset of the wall-list row offsets (uint32, rows + 1)
     int64_t wall_list;    // byte offset of the wall-list entries (one per wall node)
+    int64_t chunk_tab;    // byte offset of the chunk table (packed layout)
     int32_t nx, ny, nz;
     int32_t words;        // mask words per (y, z) row: ceil(nx / 32)
     int32_t xwords;       // extended-mask words per row
     int32_t variant;      // z-march lane layout (-1: not supported)
     int32_t tiles_y;      // z-march row groups
-    int32_t pad0;
+    int32_t pk;           // packed layout: nodes per chunk; 0 = dense layout
 };
 
 // Solid bit of node (x, y, z).
@@ -151,6 +161,22 @@ __device__ __forceinline__ uint32_t solid_bit(const uint32_t* mask, int words,
                                               int ny, int x, int y, int z) {
     const uint32_t w = mask[((int64_t)z * ny + y) * words + (x >> 5)];
     return (w >> (x & 31)) & 1u;
+}
+
+// Element index of node (x, y, z) (node index i) in the state arrays, or -1
+// when the packed layout stores no chunk for it (its chunk is all solid).
+__device__ __forceinline__ int64_t state_slot(const uint8_t* base, const SampleDev& sd, int x,
+                                              int y, int z, int64_t i) {
+    if (sd.pk == 0) return i;
+    const int ci = x / sd.pk;
+    const int groups = sd.nx / (64 * sd.pk);
+    const uint4 e = reinterpret_cast<const uint4*>(base + sd.chunk_tab)
+        [((int64_t)z * sd.ny + y) * groups + (ci >> 6)];
+    const uint64_t bits = ((uint64_t)e.y << 32) | e.x;
+    const int l = ci & 63;
+    if (!((bits >> l) & 1u)) return -1;
+    const uint64_t below = bits & ((uint64_t(1) << l) - 1u);
+    return ((int64_t)e.z + __popcll(below)) * sd.pk + (x - ci * sd.pk);
 }
 
 }  // namespace tau1

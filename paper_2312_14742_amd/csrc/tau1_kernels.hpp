@@ -152,12 +152,17 @@ __global__ void k_upload(StepArgs a, int s, const uint8_t* __restrict__ solid,
         vz = (u0 ? (T)u0[2 * len + t] : (T)0) + gh_of<T>(a, 2);
     }
     const T sr = scale_rho<P>(a), su = scale_u<P>(a);
+    const int x = (int)(i % sd.nx);
+    const int y = (int)((i / sd.nx) % sd.ny);
+    const int z = (int)(i / ((int64_t)sd.nx * sd.ny));
+    const int64_t e = state_slot(a.base, sd, x, y, z, i);
+    if (e < 0) return;  // all-solid chunk of the packed layout: no storage
     for (int b = 0; b < 2; ++b) {
         S* p = reinterpret_cast<S*>(a.base + sd.state[b]);
-        St::store(p, i, d, sr);
-        St::store(p + sd.stride, i, vx, su);
-        St::store(p + 2 * sd.stride, i, vy, su);
-        St::store(p + 3 * sd.stride, i, vz, su);
+        St::store(p, e, d, sr);
+        St::store(p + sd.stride, e, vx, su);
+        St::store(p + 2 * sd.stride, e, vy, su);
+        St::store(p + 3 * sd.stride, e, vz, su);
     }
 }
 
@@ -181,10 +186,11 @@ __global__ void k_export(StepArgs a, int s, double* __restrict__ out, int64_t i0
     double d = 0, ux = 0, uy = 0, uz = 0;
     if (!solid_bit(mask, sd.words, sd.ny, x, y, z)) {
         const S* p = reinterpret_cast<const S*>(a.base + sd.state[a.parity]);
-        d = (double)St::load(p, i, inv_scale_rho<P>(a));
-        ux = (double)St::load(p + sd.stride, i, inv_scale_u<P>(a)) - a.gh[0];
-        uy = (double)St::load(p + 2 * sd.stride, i, inv_scale_u<P>(a)) - a.gh[1];
-        uz = (double)St::load(p + 3 * sd.stride, i, inv_scale_u<P>(a)) - a.gh[2];
+        const int64_t e = state_slot(a.base, sd, x, y, z, i);  // a fluid node has a slot
+        d = (double)St::load(p, e, inv_scale_rho<P>(a));
+        ux = (double)St::load(p + sd.stride, e, inv_scale_u<P>(a)) - a.gh[0];
+        uy = (double)St::load(p + 2 * sd.stride, e, inv_scale_u<P>(a)) - a.gh[1];
+        uz = (double)St::load(p + 3 * sd.stride, e, inv_scale_u<P>(a)) - a.gh[2];
         if (!isfinite(d) || !isfinite(ux) || !isfinite(uy) || !isfinite(uz))
             atomicAdd(bad, 1);
     }
@@ -221,8 +227,9 @@ __global__ __launch_bounds__(kReduceThreads) void k_reduce_partial(StepArgs a, i
         const int y = (int)((i / sd.nx) % sd.ny);
         const int z = (int)(i / ((int64_t)sd.nx * sd.ny));
         if (solid_bit(mask, sd.words, sd.ny, x, y, z)) continue;
-        const double d = (double)St::load(p, i, inv_scale_rho<P>(a));
-        const double u = (double)St::load(pu, i, inv_scale_u<P>(a)) - a.gh[axis];
+        const int64_t e = state_slot(a.base, sd, x, y, z, i);
+        const double d = (double)St::load(p, e, inv_scale_rho<P>(a));
+        const double u = (double)St::load(pu, e, inv_scale_u<P>(a)) - a.gh[axis];
         if (!isfinite(d) || !isfinite(u)) { nb += 1; continue; }
         sdr += d;
         su += u;

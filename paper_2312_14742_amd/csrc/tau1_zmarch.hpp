@@ -60,15 +60,20 @@ constexpr int kZrThreads = 64 * kZrWaves;
 //   1  rows shared through LDS inside the workgroup (one-row-per-wave
 //      layouts; rolling prefetch for the others);
 //   2  rolling prefetch: row y-1 of the next plane is requested during this
-//      plane.
-constexpr int kNumTiles = 12;
+//      plane;
+//   3  as 1, for samples stored in the packed layout (only all-solid lane
+//      chunks are left out of memory); the tiles of a context are those of
+//      its layout: 0-2 dense, 3 packed.
+constexpr int kNumTiles = 16;
 constexpr int kTileLZ[4] = {16, 32, 64, 128};
 inline int tile_lz(int tile) { return kTileLZ[tile & 3]; }
 inline int tile_mode(int tile) { return tile / 4; }
 
 // Load schedule of a (layout, mode) pair: shared rows need one row per wave.
-constexpr bool zr_share(int g, int mode) { return mode == 1 && g == 1; }
-constexpr bool zr_roll(int g, int mode) { return mode == 2 || (mode == 1 && g != 1); }
+constexpr bool zr_share(int g, int mode) { return (mode == 1 || mode == 3) && g == 1; }
+constexpr bool zr_roll(int g, int mode) { return mode == 2 || ((mode == 1 || mode == 3) && g != 1); }
+// Packed-layout rows (mode 3 exists only for one-row-per-wave layouts).
+constexpr bool zr_packed(int g, int mode) { return mode == 3 && g == 1; }
 
 // Lane layouts (G, C, K) compiled into the kernel; nx = C * (64 / G) * K.
 struct ZrVariant {
@@ -242,7 +247,9 @@ struct RawRow {
 
 // Per-source quantities: the equilibrium of Eq. (3) minus its weight in a
 // direction with cu = c.v is w * (A + cu * (R3 + R45 * cu)) with
-// A = drho - 1.5 rho v.v, R3 = 3 rho, R45 = 4.5 rho, rho = 1 + drho.
+// A = drho - 1.5 rho v.v, R3 = 3 rho, R45 = 1.5 R3 (= 4.5 rho), rho = 1 + drho.
+// R45 is always formed from R3, so a source shared as (A, R3, v) gives the
+// same bits wherever it is evaluated.
 struct Src {
     float a, r3, r45, vx, vy, vz;
 };
@@ -253,12 +260,15 @@ __device__ __forceinline__ Src make_src(float d, float vx, float vy, float vz) {
     const float vv = vx * vx + vy * vy + vz * vz;
     s.a = __builtin_fmaf(-1.5f * rho, vv, d);
     s.r3 = 3.0f * rho;
-    s.r45 = 4.5f * rho;
+    s.r45 = 1.5f * s.r3;
     s.vx = vx;
     s.vy = vy;
     s.vz = vz;
     return s;
 }
+
+// Components of a source kept in a shared LDS row slot: A, R3, vx, vy, vz.
+constexpr int kSlotComps = 5;
 
 template <int CX, int CY, int CZ>
 __device__ __forceinline__ float feq_m(const Src& s) {
@@ -376,6 +386,11 @@ __device__ __forceinline__ int64_t uniform64(int64_t v) {
     return (int64_t)(((uint64_t)hi << 32) | lo);
 }
 
+// Chunk-table entries are read with scalar loads: the table is constant
+// while a step runs, and the row (hence the address) is wave-uniform.
+typedef unsigned int ct_u4 __attribute__((ext_vector_type(4)));
+typedef const __attribute__((address_space(4))) ct_u4 ctab_t;
+
 // Constants of one work item (one wave).
 template <int P, int G, int C, int K>
 struct ZrItem {
@@ -393,11 +408,12 @@ struct ZrItem {
     const uint32_t* woffs;  // wall-list row offsets
     float* lds_res;         // bounce-back sums [4][G * nx] of this wave
     // shared-row mode (one row per wave): the workgroup's row slots
-    // [2 planes][kZrWaves waves][4 components][nx], this wave's index, and
+    // [2 planes][kZrWaves waves][kSlotComps components][nx], this wave's index, and
     // whether rows y-1 / y+1 are the rows of the neighbouring waves
     float* lds_rows;
     int wave;
     bool share_m, share_p;
+    ctab_t* ctab;  // packed layout: chunk table of the sample (C entries per row)
 };
 
 // Solid-bit window of the wave's own row in plane zc, one per chunk: bit b
@@ -450,35 +466,120 @@ __device__ __forceinline__ void load_row(const ZrItem<P, G, C, K>& it, int row, 
     }
 }
 
-// A lane's chunks of one row in an LDS slot [4 components][nx] (one row per
-// wave): write the wave's own row, or read a neighbouring wave's.
+// A lane's chunks of one row's sources in an LDS slot [kSlotComps][nx] (one
+// row per wave): the wave publishes its own row, and it and its neighbours
+// read the sources back instead of forming them again.
 template <int P, int G, int C, int K>
-__device__ __forceinline__ void row_to_lds(const ZrItem<P, G, C, K>& it, float* slot,
+__device__ __forceinline__ void src_to_lds(const ZrItem<P, G, C, K>& it, float* slot,
                                            const RawRow<C * K>& r) {
     constexpr int RS = 64 * C * K;
 #pragma unroll
     for (int c = 0; c < C; ++c) {
+        float a[K], r3[K];
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            const Src t = make_src(r.d[c * K + j], r.vx[c * K + j], r.vy[c * K + j], r.vz[c * K + j]);
+            a[j] = t.a;
+            r3[j] = t.r3;
+        }
         float* e = slot + c * 64 * K + it.gl * K;
-        __builtin_memcpy(e, &r.d[c * K], 4 * K);
-        __builtin_memcpy(e + RS, &r.vx[c * K], 4 * K);
-        __builtin_memcpy(e + 2 * RS, &r.vy[c * K], 4 * K);
-        __builtin_memcpy(e + 3 * RS, &r.vz[c * K], 4 * K);
+        __builtin_memcpy(e, a, 4 * K);
+        __builtin_memcpy(e + RS, r3, 4 * K);
+        __builtin_memcpy(e + 2 * RS, &r.vx[c * K], 4 * K);
+        __builtin_memcpy(e + 3 * RS, &r.vy[c * K], 4 * K);
+        __builtin_memcpy(e + 4 * RS, &r.vz[c * K], 4 * K);
     }
 }
 
 template <int P, int G, int C, int K>
-__device__ __forceinline__ void row_from_lds(const ZrItem<P, G, C, K>& it, const float* slot,
-                                             RawRow<C * K>& r) {
+__device__ __forceinline__ void src_from_lds(const ZrItem<P, G, C, K>& it, const float* slot,
+                                             Src (&s)[C * K]) {
     constexpr int RS = 64 * C * K;
 #pragma unroll
     for (int c = 0; c < C; ++c) {
         const float* e = slot + c * 64 * K + it.gl * K;
-        __builtin_memcpy(&r.d[c * K], e, 4 * K);
-        __builtin_memcpy(&r.vx[c * K], e + RS, 4 * K);
-        __builtin_memcpy(&r.vy[c * K], e + 2 * RS, 4 * K);
-        __builtin_memcpy(&r.vz[c * K], e + 3 * RS, 4 * K);
+        float a[K], r3[K], vx[K], vy[K], vz[K];
+        __builtin_memcpy(a, e, 4 * K);
+        __builtin_memcpy(r3, e + RS, 4 * K);
+        __builtin_memcpy(vx, e + 2 * RS, 4 * K);
+        __builtin_memcpy(vy, e + 3 * RS, 4 * K);
+        __builtin_memcpy(vz, e + 4 * RS, 4 * K);
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            Src& t = s[c * K + j];
+            t.a = a[j];
+            t.r3 = r3[j];
+            t.r45 = 1.5f * r3[j];
+            t.vx = vx[j];
+            t.vy = vy[j];
+            t.vz = vz[j];
+        }
     }
 }
+
+// Packed layout: the chunk-table entries of one row (wave-uniform).
+template <int C>
+struct RowTab {
+    uint32_t lo[C], hi[C], rank[C];
+};
+
+template <int P, int G, int C, int K>
+__device__ __forceinline__ void row_tab(const ZrItem<P, G, C, K>& it, int row, RowTab<C>& t) {
+    ctab_t* e = it.ctab + (int64_t)row * C;
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        const ct_u4 v = e[c];
+        t.lo[c] = v.x;
+        t.hi[c] = v.y;
+        t.rank[c] = v.z;
+    }
+}
+
+// Byte offsets of the lane's chunks of a packed row: the chunk's rank among
+// the row group's fluid chunks (lanes below it with a set bit) added to the
+// group's first packed index; an all-solid chunk gets the out-of-range offset,
+// so its loads read zeros and its stores are dropped.
+template <int P, int G, int C, int K>
+__device__ __forceinline__ void chunk_voffs(const ZrItem<P, G, C, K>& it, const RowTab<C>& t,
+                                            int (&vo)[C]) {
+    constexpr uint32_t CB = (uint32_t)(K * ZrItem<P, G, C, K>::ES);
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        const uint32_t below = __builtin_amdgcn_mbcnt_hi(t.hi[c], __builtin_amdgcn_mbcnt_lo(t.lo[c], 0u));
+        const uint64_t bits = ((uint64_t)t.hi[c] << 32) | t.lo[c];
+        vo[c] = ((bits >> it.lane) & 1u) ? (int)((t.rank[c] + below) * CB) : kOob;
+    }
+}
+
+// One packed source row (whole chunks at the offsets vo).
+template <int P, int G, int C, int K>
+__device__ __forceinline__ void load_row_pk(const ZrItem<P, G, C, K>& it, const int (&vo)[C],
+                                            RawRow<C * K>& r) {
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        float t0[K], t1[K], t2[K], t3[K];
+        load_chunk<P, K>(it.pre[0], vo[c], 0, t0, it.isr);
+        load_chunk<P, K>(it.pre[1], vo[c], 0, t1, it.isu);
+        load_chunk<P, K>(it.pre[2], vo[c], 0, t2, it.isu);
+        load_chunk<P, K>(it.pre[3], vo[c], 0, t3, it.isu);
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            r.d[c * K + j] = t0[j];
+            r.vx[c * K + j] = t1[j];
+            r.vy[c * K + j] = t2[j];
+            r.vz[c * K + j] = t3[j];
+        }
+    }
+}
+
+// Packed-layout state carried along the march: the chunk-table entries of
+// the edge rows y-1 / y+1 of the current plane (fetched one plane ahead) and
+// the own row's chunk offsets of planes zs-1 (stored in this step) and zs.
+template <int C>
+struct PkPipe {
+    RowTab<C> em, ep;
+    int vst[C], vcur[C];
+};
 
 // Wall-list state carried along the march: row offsets of the planes ahead
 // (scalars) and the first 64 entries of the next plane (one per lane), loaded
@@ -496,6 +597,12 @@ __device__ __forceinline__ void wall_offsets(const ZrItem<P, G, C, K>& it, int p
                                              int& o1) {
     const int zc = wrapi(plane % it.nz, it.nz);
     const int ng = G < it.ny - it.y0 ? G : it.ny - it.y0;
+    if (ng <= 0) {
+        // a padding row group past the lattice (shared-row blocks): no wall
+        // nodes, and no row offsets to read
+        o0 = o1 = 0;
+        return;
+    }
     const int r0 = zc * it.ny + it.y0;
     o0 = __builtin_amdgcn_readfirstlane((int)it.woffs[r0]);
     o1 = __builtin_amdgcn_readfirstlane((int)it.woffs[r0 + ng]);
@@ -554,9 +661,9 @@ __device__ __forceinline__ void wall_state(const ZrItem<P, G, C, K>& it, typenam
 // through LDS back to the owners, which add them to the plane's partial sums
 // and clear their slots for the next plane.
 //
-// Shared-row mode (state != nullptr): the node's state comes from the wave's
-// own row slot in LDS, and the sums go through `res`, a slot the owners clear
-// first.  Otherwise the state of the first 64 nodes is v0 (loaded at the
+// Shared-row mode (state != nullptr): the node's source terms come from the
+// wave's own row slot in LDS, and the sums go through `res`, a slot the owners
+// clear first.  Otherwise the state of the first 64 nodes is v0 (loaded at the
 // start of the step), later ones are loaded here, and `res` is the wave's
 // sum area, which the owners clear after reading.
 template <int Q, int P, int G, int C, int K>
@@ -590,13 +697,17 @@ __device__ __forceinline__ void bounce_list(const ZrItem<P, G, C, K>& it, Plane<
         if (i < total) {
             const int n = (int)((e >> 10) & 3u) * it.nx + (int)(e & 1023u);
             const uint32_t links = (uint32_t)(e >> 12);
+            Src sw;
             if (state) {
-                v[0] = state[n];
-                v[1] = state[RS + n];
-                v[2] = state[2 * RS + n];
-                v[3] = state[3 * RS + n];
+                sw.a = state[n];
+                sw.r3 = state[RS + n];
+                sw.r45 = 1.5f * sw.r3;
+                sw.vx = state[2 * RS + n];
+                sw.vy = state[3 * RS + n];
+                sw.vz = state[4 * RS + n];
+            } else {
+                sw = make_src(v[0], v[1], v[2], v[3]);
             }
-            const Src sw = make_src(v[0], v[1], v[2], v[3]);
             float sd[3] = {0.f, 0.f, 0.f};
             float sj[3][3] = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};
             bounce_sum<Q>(sw, links, sd, sj);
@@ -633,16 +744,18 @@ __device__ __forceinline__ void bounce_list(const ZrItem<P, G, C, K>& it, Plane<
 // each wave loads only its own row (requested at the end of the previous
 // plane, `ahead`), publishes it in an LDS slot, and after one workgroup
 // barrier per plane reads rows y-1 / y+1 from its neighbours' slots; only the
-// block's edge rows come from memory.  Rolling prefetch (mode 2, and mode 1
-// with G > 1): row y-1 of the next plane (`ahead`) is requested during this
-// plane.
+// block's edge rows come from memory.  Mode 3 is mode 1 on the packed layout:
+// rows are read and written at their chunks' packed offsets.  Rolling
+// prefetch (mode 2, and modes 1 and 3 with G > 1): row y-1 of the next plane
+// (`ahead`) is requested during this plane.
 template <int Q, int P, int G, int C, int K, int MODE>
 __device__ __forceinline__ void zr_step(const ZrItem<P, G, C, K>& it, int zs, Planes<C * K> pl,
                                         uint32_t (&win_next)[C], uint32_t& fluid_prev,
-                                        WallPipe<Q>& wp, RawRow<C * K>& ahead) {
+                                        WallPipe<Q>& wp, RawRow<C * K>& ahead, PkPipe<C>& pk) {
     constexpr int PX = C * K;
     constexpr bool SHARE = zr_share(G, MODE);
     constexpr bool ROLL = zr_roll(G, MODE);
+    constexpr bool PK = zr_packed(G, MODE);
     constexpr int RS = 64 * PX;
     const int z0 = it.z0, z1 = it.z1, ny = it.ny, nz = it.nz;
     const int zmask = ((zs - 1 >= z0 && zs - 1 < z1) ? 1 : 0) |
@@ -659,6 +772,14 @@ __device__ __forceinline__ void zr_step(const ZrItem<P, G, C, K>& it, int zs, Pl
     const auto e_next = wall_load<Q>(it.wl, wp.next0 + it.lane, it.lane < wp.next1 - wp.next0);
     int nn0, nn1;
     wall_offsets(it, zs + 2, nn0, nn1);
+    // packed layout: chunk tables of the next plane's own and edge rows
+    RowTab<C> tn_own, tn_m, tn_p;
+    if constexpr (PK) {
+        const int zn = wrapi((zs + 1) % nz, nz) * ny;
+        row_tab(it, zn + it.yc, tn_own);
+        row_tab(it, zn + it.ym, tn_m);
+        row_tab(it, zn + it.yp, tn_p);
+    }
     // state of this plane's first 64 wall nodes, used by the bounce-back below
     float wv[4] = {0.f, 0.f, 0.f, 0.f};
     if constexpr (!SHARE)
@@ -669,15 +790,25 @@ __device__ __forceinline__ void zr_step(const ZrItem<P, G, C, K>& it, int zs, Pl
     if constexpr (SHARE) {
         // slots of this plane (parity of zs) and of the next one
         const int b = zs & 1;
-        own = it.lds_rows + (b * kZrWaves + it.wave) * 4 * RS;
-        spare = it.lds_rows + ((b ^ 1) * kZrWaves + it.wave) * 4 * RS;
-        ro = ahead;
-        if (!it.share_m) load_row(it, rm_, rm);
-        if (!it.share_p) load_row(it, rp_, rp);
-        row_to_lds(it, own, ro);
+        own = it.lds_rows + (b * kZrWaves + it.wave) * kSlotComps * RS;
+        spare = it.lds_rows + ((b ^ 1) * kZrWaves + it.wave) * kSlotComps * RS;
+        src_to_lds(it, own, ahead);
+        if constexpr (PK) {
+            if (!it.share_m) {
+                int vo[C];
+                chunk_voffs(it, pk.em, vo);
+                load_row_pk(it, vo, rm);
+            }
+            if (!it.share_p) {
+                int vo[C];
+                chunk_voffs(it, pk.ep, vo);
+                load_row_pk(it, vo, rp);
+            }
+        } else {
+            if (!it.share_m) load_row(it, rm_, rm);
+            if (!it.share_p) load_row(it, rp_, rp);
+        }
         __syncthreads();
-        if (it.share_m) row_from_lds(it, it.lds_rows + (b * kZrWaves + it.wave - 1) * 4 * RS, rm);
-        if (it.share_p) row_from_lds(it, it.lds_rows + (b * kZrWaves + it.wave + 1) * 4 * RS, rp);
     } else if constexpr (ROLL) {
         rm = ahead;
         load_row(it, rp_, rp);
@@ -688,16 +819,24 @@ __device__ __forceinline__ void zr_step(const ZrItem<P, G, C, K>& it, int zs, Pl
     // ---- neighbour rows: y-1 sends its c_y = +1 directions, y+1 its c_y = -1
     {
         Src s[PX];
+        if (SHARE && it.share_m) {
+            src_from_lds(it, own - kSlotComps * RS, s);
+        } else {
 #pragma unroll
-        for (int j = 0; j < PX; ++j) s[j] = make_src(rm.d[j], rm.vx[j], rm.vy[j], rm.vz[j]);
+            for (int j = 0; j < PX; ++j) s[j] = make_src(rm.d[j], rm.vx[j], rm.vy[j], rm.vz[j]);
+        }
         push_row<Q, 1, G, C, K>(pl, s, zmask, it.first_lane, it.last_lane);
     }
     if constexpr (ROLL) load_row(it, ro_, ro);
     else if constexpr (!SHARE) load_row(it, rp_, rp);
     {
         Src s[PX];
+        if (SHARE && it.share_p) {
+            src_from_lds(it, own + kSlotComps * RS, s);
+        } else {
 #pragma unroll
-        for (int j = 0; j < PX; ++j) s[j] = make_src(rp.d[j], rp.vx[j], rp.vy[j], rp.vz[j]);
+            for (int j = 0; j < PX; ++j) s[j] = make_src(rp.d[j], rp.vx[j], rp.vy[j], rp.vz[j]);
+        }
         push_row<Q, -1, G, C, K>(pl, s, zmask, it.first_lane, it.last_lane);
     }
     if constexpr (ROLL) load_row(it, wrapi((zs + 1) % nz, nz) * ny + it.ym, ahead);
@@ -705,8 +844,12 @@ __device__ __forceinline__ void zr_step(const ZrItem<P, G, C, K>& it, int zs, Pl
     // ---- own row: c_y = 0 directions and the rest population
     {
         Src s[PX];
+        if constexpr (SHARE) {
+            src_from_lds(it, own, s);
+        } else {
 #pragma unroll
-        for (int j = 0; j < PX; ++j) s[j] = make_src(ro.d[j], ro.vx[j], ro.vy[j], ro.vz[j]);
+            for (int j = 0; j < PX; ++j) s[j] = make_src(ro.d[j], ro.vx[j], ro.vy[j], ro.vz[j]);
+        }
         push_row<Q, 0, G, C, K>(pl, s, zmask, it.first_lane, it.last_lane);
         if (zmask & 2) {
             constexpr float w0 = (float)weight<Q>(0);
@@ -743,17 +886,30 @@ __device__ __forceinline__ void zr_step(const ZrItem<P, G, C, K>& it, int zs, Pl
                 oy[j] = f ? __builtin_fmaf(pl.m.v[2][sl], r, it.gy) : 0.0f;
                 oz[j] = f ? __builtin_fmaf(pl.m.v[3][sl], r, it.gz) : 0.0f;
             }
-            const int vo = it.voff[c] + (G == 1 ? 0 : ro2);
-            store_chunk<P, K>(it.post[0], vo, so, od, it.sr);
-            store_chunk<P, K>(it.post[1], vo, so, ox, it.su);
-            store_chunk<P, K>(it.post[2], vo, so, oy, it.su);
-            store_chunk<P, K>(it.post[3], vo, so, oz, it.su);
+            const int vo = PK ? pk.vst[c] : it.voff[c] + (G == 1 ? 0 : ro2);
+            store_chunk<P, K>(it.post[0], vo, PK ? 0 : so, od, it.sr);
+            store_chunk<P, K>(it.post[1], vo, PK ? 0 : so, ox, it.su);
+            store_chunk<P, K>(it.post[2], vo, PK ? 0 : so, oy, it.su);
+            store_chunk<P, K>(it.post[3], vo, PK ? 0 : so, oz, it.su);
         }
     }
     fluid_prev = fown;
     // shared rows: the next plane's own row, requested once this plane's
     // registers are free (it lands while the next step starts)
-    if constexpr (SHARE) load_row(it, wrapi((zs + 1) % nz, nz) * ny + it.yc, ahead);
+    if constexpr (PK) {
+        int vn[C];
+        chunk_voffs(it, tn_own, vn);
+        load_row_pk(it, vn, ahead);
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            pk.vst[c] = pk.vcur[c];
+            pk.vcur[c] = vn[c];
+        }
+        pk.em = tn_m;
+        pk.ep = tn_p;
+    } else if constexpr (SHARE) {
+        load_row(it, wrapi((zs + 1) % nz, nz) * ny + it.yc, ahead);
+    }
 }
 
 template <int PX>
@@ -826,6 +982,7 @@ __device__ __forceinline__ void zr_item(const StepArgs& a, const SampleDev* sd, 
     // consecutive rows, and a row past ny wraps to a row outside the block
     it.share_m = wave > 0;
     it.share_p = wave < kZrWaves - 1 && y + 1 < it.ny;
+    it.ctab = (ctab_t*)(a.base + uniform64(sd->chunk_tab));
 
     Plane<PX> A, B, Cp;
     zero_plane(A);
@@ -841,17 +998,29 @@ __device__ __forceinline__ void zr_item(const StepArgs& a, const SampleDev* sd, 
     // row requested ahead for the first source plane: the own row (shared
     // rows) or row y-1 (rolling prefetch)
     RawRow<PX> rm;
-    if constexpr (MODE != 0)
+    PkPipe<C> pk;
+    if constexpr (zr_packed(G, MODE)) {
+        const int zp = wrapi((z0 - 1) % it.nz, it.nz) * it.ny;
+        RowTab<C> t;
+        row_tab(it, zp + it.yc, t);
+        chunk_voffs(it, t, pk.vcur);
+#pragma unroll
+        for (int c = 0; c < C; ++c) pk.vst[c] = kOob;  // plane z0 - 2 is not stored
+        row_tab(it, zp + it.ym, pk.em);
+        row_tab(it, zp + it.yp, pk.ep);
+        load_row_pk(it, pk.vcur, rm);
+    } else if constexpr (MODE != 0) {
         load_row(it, wrapi((z0 - 1) % it.nz, it.nz) * it.ny + (zr_share(G, MODE) ? it.yc : it.ym), rm);
+    }
     int zs = z0 - 1;
     while (true) {
-        zr_step<Q, P, G, C, K, MODE>(it, zs, Planes<PX>{A, B, Cp}, win_next, fluid_prev, wp, rm);
+        zr_step<Q, P, G, C, K, MODE>(it, zs, Planes<PX>{A, B, Cp}, win_next, fluid_prev, wp, rm, pk);
         zero_plane(A);
         if (++zs > z1) break;
-        zr_step<Q, P, G, C, K, MODE>(it, zs, Planes<PX>{B, Cp, A}, win_next, fluid_prev, wp, rm);
+        zr_step<Q, P, G, C, K, MODE>(it, zs, Planes<PX>{B, Cp, A}, win_next, fluid_prev, wp, rm, pk);
         zero_plane(B);
         if (++zs > z1) break;
-        zr_step<Q, P, G, C, K, MODE>(it, zs, Planes<PX>{Cp, A, B}, win_next, fluid_prev, wp, rm);
+        zr_step<Q, P, G, C, K, MODE>(it, zs, Planes<PX>{Cp, A, B}, win_next, fluid_prev, wp, rm, pk);
         zero_plane(Cp);
         if (++zs > z1) break;
     }
@@ -869,9 +1038,10 @@ __global__ __launch_bounds__(kZrThreads) void k_zmarch(StepArgs a) {
     constexpr int G = kVariants[V].g, C = kVariants[V].c, K = kVariants[V].k;
     constexpr int kPX = C * K;
     constexpr bool kShare = zr_share(G, MODE);
-    // shared rows: [2 planes][kZrWaves][4][64 * kPX] (the bounce-back sums use
-    // the other plane's slot); otherwise bounce-back sums [kZrWaves][4][64 * kPX]
-    constexpr int kLds = (kShare ? 2 : 1) * kZrWaves * 4 * kPX * 64;
+    // shared rows: [2 planes][kZrWaves][kSlotComps][64 * kPX] (the bounce-back
+    // sums use the other plane's slot); otherwise bounce-back sums
+    // [kZrWaves][4][64 * kPX]
+    constexpr int kLds = kShare ? 2 * kZrWaves * kSlotComps * kPX * 64 : kZrWaves * 4 * kPX * 64;
     __shared__ float lds_all[kLds];
     const int wave = threadIdx.x >> 6;
     float* lds_wave = lds_all + wave * 4 * kPX * 64;
@@ -913,11 +1083,14 @@ inline int zr_xwords(int nx) { return (nx + 2 + 31) / 32 + 1; }
 
 inline bool zmarch_precision_ok(int prec) { return prec == kF32 || prec == kF16 || prec == kBF16; }
 
-inline bool zmarch_tile_ok(int, int prec, int tile) {
-    return zmarch_precision_ok(prec) && tile >= 0 && tile < kNumTiles;
+// Tiles of a context: mode 3 exactly when its samples use the packed layout.
+inline bool zmarch_tile_ok(int prec, bool packed, int tile) {
+    return zmarch_precision_ok(prec) && tile >= 0 && tile < kNumTiles &&
+           (tile_mode(tile) == 3) == packed;
 }
 
-inline int zmarch_default_tile(int, int) { return 2; }  // z-segments of 64 planes
+// z-segments of 64 planes
+inline int zmarch_default_tile(bool packed) { return packed ? 14 : 2; }
 
 inline void* pick_zmarch(int q, int p, int variant, int mode) {
     switch (q * 10 + p) {
@@ -1019,7 +1192,7 @@ inline int64_t size_bucket(int64_t n) {
     return b;
 }
 
-inline int zmarch_cache_lookup(const char* path, int q, int p, int64_t nodes) {
+inline int zmarch_cache_lookup(const char* path, int q, int p, int64_t nodes, bool packed) {
     FILE* f = std::fopen(path, "r");
     if (!f) return -1;
     char line[256];
@@ -1032,8 +1205,8 @@ inline int zmarch_cache_lookup(const char* path, int q, int p, int64_t nodes) {
         char arch[64];
         if (std::sscanf(line, "tau1 %63s q%d p%d n%lld tile %d ms %f", arch, &qq, &pp, &nb, &tile,
                         &ms) == 6 &&
-            std::strcmp(arch, "gfx950") == 0 && qq == q && pp == p && nb == bucket && tile >= 0 &&
-            tile < kNumTiles)
+            std::strcmp(arch, "gfx950") == 0 && qq == q && pp == p && nb == bucket &&
+            zmarch_tile_ok(p, packed, tile))
             found = tile;
     }
     std::fclose(f);

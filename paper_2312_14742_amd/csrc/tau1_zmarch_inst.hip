@@ -15,18 +15,20 @@ namespace tau1 {
 #define TAU1_CAT2(a, b, c) a##b##_##c
 #define TAU1_CAT(a, b, c) TAU1_CAT2(a, b, c)
 
-// Kernel of layout V for load mode 0-2; mode 1 on a multi-row layout is the
-// same schedule as mode 2 and uses that instance.
+// Kernel of layout V for load mode 0-3; modes 1 and 3 on a multi-row layout
+// are the same schedule as mode 2 (dense layout) and use that instance.
 template <int V>
 void* zm_pick(int mode) {
     if (mode == 0) return reinterpret_cast<void*>(&k_zmarch<TAU1_Q, TAU1_P, V, 0>);
-    if constexpr (kVariants[V].g == 1)
+    if constexpr (kVariants[V].g == 1) {
         if (mode == 1) return reinterpret_cast<void*>(&k_zmarch<TAU1_Q, TAU1_P, V, 1>);
+        if (mode == 3) return reinterpret_cast<void*>(&k_zmarch<TAU1_Q, TAU1_P, V, 3>);
+    }
     return reinterpret_cast<void*>(&k_zmarch<TAU1_Q, TAU1_P, V, 2>);
 }
 
 void* TAU1_CAT(zm_kernel_, TAU1_Q, TAU1_P)(int variant, int mode) {
-    if (mode < 0 || mode > 2) return nullptr;
+    if (mode < 0 || mode > 3) return nullptr;
     switch (variant) {
 #define TAU1_V(V) case V: return zm_pick<V>(mode);
         TAU1_V(0) TAU1_V(1) TAU1_V(2) TAU1_V(3) TAU1_V(4) TAU1_V(5) TAU1_V(6) TAU1_V(7)

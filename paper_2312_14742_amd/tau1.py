@@ -56,13 +56,15 @@ class tau1_desc(ctypes.Structure):
                 ("kernel", ctypes.c_int32), ("tile", ctypes.c_int32),
                 ("f16_log2_scale_rho", ctypes.c_int32),
                 ("f16_log2_scale_u", ctypes.c_int32),
-                ("tune_cache", ctypes.c_char_p)]
+                ("tune_cache", ctypes.c_char_p),
+                ("layout", ctypes.c_int32)]
 
 
 class tau1_info(ctypes.Structure):
     _fields_ = [("lattice", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("n_samples", ctypes.c_int32), ("kernel", ctypes.c_int32),
                 ("tile", ctypes.c_int32), ("graph_chunk", ctypes.c_int32),
+                ("layout", ctypes.c_int32),
                 ("n_nodes", ctypes.c_int64), ("n_fluid", ctypes.c_int64),
                 ("steps_done", ctypes.c_int64), ("bytes_per_step", ctypes.c_double)]
 
@@ -147,7 +149,7 @@ class Sample:
 
 
 def _desc(samples, lattice, precision, g, graph_chunk, kernel, tile, f16_scales,
-          tune_cache):
+          tune_cache, layout=-1):
     arr = (tau1_sample * len(samples))(*[s.c_struct() for s in samples])
     d = tau1_desc()
     d.lattice = int(lattice)
@@ -162,15 +164,16 @@ def _desc(samples, lattice, precision, g, graph_chunk, kernel, tile, f16_scales,
     d.f16_log2_scale_rho = int(f16_scales[0])
     d.f16_log2_scale_u = int(f16_scales[1])
     d.tune_cache = None if tune_cache is None else os.fsencode(tune_cache)
+    d.layout = int(layout)
     return d, arr
 
 
 def workspace_size(samples, lattice=19, precision="f32", g=(0.0, 0.0, 0.0),
-                   graph_chunk=0, kernel=-1, tile=-1, f16_scales=(0, 0)) -> int:
+                   graph_chunk=0, kernel=-1, tile=-1, f16_scales=(0, 0), layout=-1) -> int:
     """Device bytes tau1_create needs (host-only call)."""
     samples = [s if isinstance(s, Sample) else Sample(*s) for s in samples]
     d, keep = _desc(samples, lattice, precision, g, graph_chunk, kernel, tile,
-                    f16_scales, None)
+                    f16_scales, None, layout)
     n = ctypes.c_size_t(0)
     _check(_lib().tau1_workspace_size(ctypes.byref(d), ctypes.byref(n)),
            "tau1_workspace_size")
@@ -183,11 +186,13 @@ class Sim:
 
     ``precision`` is one of "f64", "f32", "f16", "bf16".  ``kernel`` -1 picks
     automatically, 0 forces the per-node gather kernel, 1 the z-march tiles.
+    ``layout`` -1 picks the state layout automatically, 0 is dense, 1 packed
+    (all-solid lane chunks not stored).
     """
 
     def __init__(self, samples, lattice=19, precision="f32", g=(0.0, 0.0, 0.0),
                  graph_chunk=0, kernel=-1, tile=-1, f16_scales=(0, 0),
-                 tune_cache=None, device="cuda:0"):
+                 tune_cache=None, device="cuda:0", layout=-1):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("Tau1 Sim needs a ROCm GPU (torch.cuda is unavailable)")
@@ -199,7 +204,7 @@ class Sim:
         self.g = tuple(float(x) for x in g)
         lib = _lib()
         d, keep = _desc(self.samples, lattice, precision, g, graph_chunk, kernel, tile,
-                        f16_scales, tune_cache)
+                        f16_scales, tune_cache, layout)
         n = ctypes.c_size_t(0)
         _check(lib.tau1_workspace_size(ctypes.byref(d), ctypes.byref(n)),
                "tau1_workspace_size")
