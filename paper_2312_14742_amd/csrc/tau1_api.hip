@@ -139,16 +139,31 @@ Plan make_plan(const tau1_desc* d, bool tables) {
     const bool zm = zmarch_supported(d->lattice, d->precision, p.s.data(), d->n_samples);
     const bool auto_pack = d->precision == kF32 && (d->tile < 0 || tile_mode(d->tile) == 3);
     const bool pack = zm && d->kernel != 0 && (d->layout == 1 || (d->layout < 0 && auto_pack));
+    // All samples of one lane layout share a launch, so a layout is packed
+    // only if each of its samples fits: the step kernel addresses the four
+    // packed arrays of a buffer with 32-bit offsets from one base.
+    std::vector<int64_t> pstride(d->n_samples, 0);
+    bool layout_ok[kNumVariants];
+    for (int v = 0; v < kNumVariants; ++v) layout_ok[v] = pack && kVariants[v].g == 1;
+    for (int i = 0; pack && i < d->n_samples; ++i) {
+        const SampleDev& sd = p.s[i].dev;
+        if (!layout_ok[sd.variant]) continue;
+        const int k = kVariants[sd.variant].k;
+        const int64_t nch = chunk_table(d->samples[i], k, kVariants[sd.variant].c, nullptr);
+        pstride[i] = (int64_t)(align_up((size_t)std::max<int64_t>(nch * k, 1) * sz, kAlign) / sz);
+        if (4 * pstride[i] * sz + 65536 > (int64_t)kOob) layout_ok[sd.variant] = false;
+    }
     for (int i = 0; pack && i < d->n_samples; ++i) {
         SampleDev& sd = p.s[i].dev;
-        if (kVariants[sd.variant].g != 1) continue;
+        if (!layout_ok[sd.variant]) continue;
         const int k = kVariants[sd.variant].k;
         const int groups = kVariants[sd.variant].c;
-        if (tables) p.s[i].ctab.assign((size_t)sd.ny * sd.nz * groups * 4, 0u);
-        const int64_t nch = chunk_table(d->samples[i], k, groups,
-                                        tables ? p.s[i].ctab.data() : nullptr);
+        if (tables) {
+            p.s[i].ctab.assign((size_t)sd.ny * sd.nz * groups * 4, 0u);
+            chunk_table(d->samples[i], k, groups, p.s[i].ctab.data());
+        }
         sd.pk = k;
-        sd.stride = (int64_t)(align_up((size_t)std::max<int64_t>(nch * k, 1) * sz, kAlign) / sz);
+        sd.stride = pstride[i];
         p.packed = true;
     }
     p.pack_refused = d->layout == 1 && !p.packed;
@@ -208,6 +223,7 @@ struct tau1_ctx {
     // z-march launches: one per lane layout present, each over its samples' items
     struct ZGroup {
         int variant;
+        bool packed;  // its samples use the packed layout
         StepArgs args[2];
     };
     std::vector<ZGroup> zgroups;
@@ -274,7 +290,9 @@ Launch step_launch(const tau1_ctx* ctx, int kernel, int tile, int g) {
     Launch l{};
     if (kernel == 1) {
         const auto& grp = ctx->zgroups[g];
-        l.fn = pick_zmarch(ctx->lattice, ctx->precision, grp.variant, tile_mode(tile));
+        // a dense one-row layout in a packed context runs the dense shared-row schedule
+        const int mode = tile_mode(tile) == 3 && !grp.packed ? 1 : tile_mode(tile);
+        l.fn = pick_zmarch(ctx->lattice, ctx->precision, grp.variant, mode);
         l.block = dim3(zmarch_threads(tile));
         l.grid = dim3((unsigned)zmarch_grid(grp.args[0].ntiles, tile));
         l.shmem = 0;
@@ -538,6 +556,9 @@ tau1_status set_tile(tau1_ctx* ctx, int tile) {
         tl.insert(tl.end(), part.begin(), part.end());
         tau1_ctx::ZGroup g;
         g.variant = v;
+        g.packed = false;
+        for (const auto& sh : ctx->plan.s)
+            if (sh.dev.variant == v && sh.dev.pk) g.packed = true;
         for (int p = 0; p < 2; ++p) {
             g.args[p] = ctx->args[p];
             g.args[p].tiles = reinterpret_cast<const int32_t*>(ctx->base + ctx->plan.tiles_off) +

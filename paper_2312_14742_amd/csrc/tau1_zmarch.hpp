@@ -397,7 +397,11 @@ struct ZrItem {
     static constexpr int Lg = 64 / G;
     static constexpr int PX = C * K;
     static constexpr int ES = (int)sizeof(typename Storage<P>::S);
+    // state arrays drho | vx | vy | vz of the read and the written buffer; the
+    // packed layout uses one resource per buffer over all four arrays
+    // (pre[0], post[0]) and addresses array c at c * abytes
     rsrc_t pre[4], post[4], xm, wl;
+    int abytes;
     int lane, gl;
     bool first_lane, last_lane, active;
     int nx, ny, nz, xw, z0, z1;
@@ -559,9 +563,9 @@ __device__ __forceinline__ void load_row_pk(const ZrItem<P, G, C, K>& it, const 
     for (int c = 0; c < C; ++c) {
         float t0[K], t1[K], t2[K], t3[K];
         load_chunk<P, K>(it.pre[0], vo[c], 0, t0, it.isr);
-        load_chunk<P, K>(it.pre[1], vo[c], 0, t1, it.isu);
-        load_chunk<P, K>(it.pre[2], vo[c], 0, t2, it.isu);
-        load_chunk<P, K>(it.pre[3], vo[c], 0, t3, it.isu);
+        load_chunk<P, K>(it.pre[0], vo[c], it.abytes, t1, it.isu);
+        load_chunk<P, K>(it.pre[0], vo[c], 2 * it.abytes, t2, it.isu);
+        load_chunk<P, K>(it.pre[0], vo[c], 3 * it.abytes, t3, it.isu);
 #pragma unroll
         for (int j = 0; j < K; ++j) {
             r.d[c * K + j] = t0[j];
@@ -572,12 +576,13 @@ __device__ __forceinline__ void load_row_pk(const ZrItem<P, G, C, K>& it, const 
     }
 }
 
-// Packed-layout state carried along the march: the chunk-table entries of
-// the edge rows y-1 / y+1 of the current plane (fetched one plane ahead) and
-// the own row's chunk offsets of planes zs-1 (stored in this step) and zs.
+// Packed-layout state carried along the march: the lane's chunk offsets in
+// the edge rows y-1 / y+1 of the current plane (their table entries are
+// fetched one plane ahead) and in the own row of planes zs-1 (stored in this
+// step) and zs.
 template <int C>
 struct PkPipe {
-    RowTab<C> em, ep;
+    int vm[C], vp[C];
     int vst[C], vcur[C];
 };
 
@@ -746,8 +751,8 @@ __device__ __forceinline__ void bounce_list(const ZrItem<P, G, C, K>& it, Plane<
 // barrier per plane reads rows y-1 / y+1 from its neighbours' slots; only the
 // block's edge rows come from memory.  Mode 3 is mode 1 on the packed layout:
 // rows are read and written at their chunks' packed offsets.  Rolling
-// prefetch (mode 2, and modes 1 and 3 with G > 1): row y-1 of the next plane
-// (`ahead`) is requested during this plane.
+// prefetch (mode 2, and modes 1 and 3 with G > 1): the own row of the next
+// plane (`ahead`) is requested during this plane.
 template <int Q, int P, int G, int C, int K, int MODE>
 __device__ __forceinline__ void zr_step(const ZrItem<P, G, C, K>& it, int zs, Planes<C * K> pl,
                                         uint32_t (&win_next)[C], uint32_t& fluid_prev,
@@ -793,54 +798,25 @@ __device__ __forceinline__ void zr_step(const ZrItem<P, G, C, K>& it, int zs, Pl
         own = it.lds_rows + (b * kZrWaves + it.wave) * kSlotComps * RS;
         spare = it.lds_rows + ((b ^ 1) * kZrWaves + it.wave) * kSlotComps * RS;
         src_to_lds(it, own, ahead);
+        // the block's edge rows come from memory; they are pushed after the
+        // own row, which gives their loads time to land
         if constexpr (PK) {
-            if (!it.share_m) {
-                int vo[C];
-                chunk_voffs(it, pk.em, vo);
-                load_row_pk(it, vo, rm);
-            }
-            if (!it.share_p) {
-                int vo[C];
-                chunk_voffs(it, pk.ep, vo);
-                load_row_pk(it, vo, rp);
-            }
+            if (!it.share_m) load_row_pk(it, pk.vm, rm);
+            if (!it.share_p) load_row_pk(it, pk.vp, rp);
         } else {
             if (!it.share_m) load_row(it, rm_, rm);
             if (!it.share_p) load_row(it, rp_, rp);
         }
         __syncthreads();
     } else if constexpr (ROLL) {
-        rm = ahead;
-        load_row(it, rp_, rp);
-    } else {
+        ro = ahead;
         load_row(it, rm_, rm);
+    } else {
+        load_row(it, ro_, ro);
     }
 
-    // ---- neighbour rows: y-1 sends its c_y = +1 directions, y+1 its c_y = -1
-    {
-        Src s[PX];
-        if (SHARE && it.share_m) {
-            src_from_lds(it, own - kSlotComps * RS, s);
-        } else {
-#pragma unroll
-            for (int j = 0; j < PX; ++j) s[j] = make_src(rm.d[j], rm.vx[j], rm.vy[j], rm.vz[j]);
-        }
-        push_row<Q, 1, G, C, K>(pl, s, zmask, it.first_lane, it.last_lane);
-    }
-    if constexpr (ROLL) load_row(it, ro_, ro);
-    else if constexpr (!SHARE) load_row(it, rp_, rp);
-    {
-        Src s[PX];
-        if (SHARE && it.share_p) {
-            src_from_lds(it, own + kSlotComps * RS, s);
-        } else {
-#pragma unroll
-            for (int j = 0; j < PX; ++j) s[j] = make_src(rp.d[j], rp.vx[j], rp.vy[j], rp.vz[j]);
-        }
-        push_row<Q, -1, G, C, K>(pl, s, zmask, it.first_lane, it.last_lane);
-    }
-    if constexpr (ROLL) load_row(it, wrapi((zs + 1) % nz, nz) * ny + it.ym, ahead);
-    else if constexpr (!SHARE) load_row(it, ro_, ro);
+    // Every schedule adds the rows in the same order -- own row, row y-1,
+    // row y+1 -- so every tile forms each sum with the same roundings.
     // ---- own row: c_y = 0 directions and the rest population
     {
         Src s[PX];
@@ -856,6 +832,33 @@ __device__ __forceinline__ void zr_step(const ZrItem<P, G, C, K>& it, int zs, Pl
 #pragma unroll
             for (int j = 0; j < PX; ++j) pl.c.v[0][j] = __builtin_fmaf(w0, s[j].a, pl.c.v[0][j]);
         }
+    }
+    // rolling prefetch: each row is requested one push ahead of its use, the
+    // next plane's own row once this one's registers are free
+    if constexpr (ROLL) load_row(it, rp_, rp);
+    else if constexpr (!SHARE) load_row(it, rm_, rm);
+    // ---- neighbour rows: y-1 sends its c_y = +1 directions, y+1 its c_y = -1
+    {
+        Src s[PX];
+        if (SHARE && it.share_m) {
+            src_from_lds(it, own - kSlotComps * RS, s);
+        } else {
+#pragma unroll
+            for (int j = 0; j < PX; ++j) s[j] = make_src(rm.d[j], rm.vx[j], rm.vy[j], rm.vz[j]);
+        }
+        push_row<Q, 1, G, C, K>(pl, s, zmask, it.first_lane, it.last_lane);
+    }
+    if constexpr (ROLL) load_row(it, wrapi((zs + 1) % nz, nz) * ny + it.yc, ahead);
+    else if constexpr (!SHARE) load_row(it, rp_, rp);
+    {
+        Src s[PX];
+        if (SHARE && it.share_p) {
+            src_from_lds(it, own + kSlotComps * RS, s);
+        } else {
+#pragma unroll
+            for (int j = 0; j < PX; ++j) s[j] = make_src(rp.d[j], rp.vx[j], rp.vy[j], rp.vz[j]);
+        }
+        push_row<Q, -1, G, C, K>(pl, s, zmask, it.first_lane, it.last_lane);
     }
     // ---- halfway bounce-back at this plane's wall nodes (static list)
     if (zmask & 2)
@@ -887,10 +890,20 @@ __device__ __forceinline__ void zr_step(const ZrItem<P, G, C, K>& it, int zs, Pl
                 oz[j] = f ? __builtin_fmaf(pl.m.v[3][sl], r, it.gz) : 0.0f;
             }
             const int vo = PK ? pk.vst[c] : it.voff[c] + (G == 1 ? 0 : ro2);
-            store_chunk<P, K>(it.post[0], vo, PK ? 0 : so, od, it.sr);
-            store_chunk<P, K>(it.post[1], vo, PK ? 0 : so, ox, it.su);
-            store_chunk<P, K>(it.post[2], vo, PK ? 0 : so, oy, it.su);
-            store_chunk<P, K>(it.post[3], vo, PK ? 0 : so, oz, it.su);
+            if constexpr (PK) {
+                // an all-solid chunk's offset stays out of range in every array
+                // (unsigned 32-bit sums below 2^32: 4 * abytes <= kOob)
+                const uint32_t u = (uint32_t)vo, ab = (uint32_t)it.abytes;
+                store_chunk<P, K>(it.post[0], vo, 0, od, it.sr);
+                store_chunk<P, K>(it.post[0], (int)(u + ab), 0, ox, it.su);
+                store_chunk<P, K>(it.post[0], (int)(u + 2 * ab), 0, oy, it.su);
+                store_chunk<P, K>(it.post[0], (int)(u + 3 * ab), 0, oz, it.su);
+            } else {
+                store_chunk<P, K>(it.post[0], vo, so, od, it.sr);
+                store_chunk<P, K>(it.post[1], vo, so, ox, it.su);
+                store_chunk<P, K>(it.post[2], vo, so, oy, it.su);
+                store_chunk<P, K>(it.post[3], vo, so, oz, it.su);
+            }
         }
     }
     fluid_prev = fown;
@@ -905,8 +918,8 @@ __device__ __forceinline__ void zr_step(const ZrItem<P, G, C, K>& it, int zs, Pl
             pk.vst[c] = pk.vcur[c];
             pk.vcur[c] = vn[c];
         }
-        pk.em = tn_m;
-        pk.ep = tn_p;
+        if (!it.share_m) chunk_voffs(it, tn_m, pk.vm);
+        if (!it.share_p) chunk_voffs(it, tn_p, pk.vp);
     } else if constexpr (SHARE) {
         load_row(it, wrapi((zs + 1) % nz, nz) * ny + it.yc, ahead);
     }
@@ -953,13 +966,14 @@ __device__ __forceinline__ void zr_item(const StepArgs& a, const SampleDev* sd, 
     it.yp = wrapi(it.yc + 1, it.ny);
     const int64_t stride = uniform64(sd->stride);
     const uint32_t abytes = (uint32_t)(stride * It::ES);
+    it.abytes = (int)abytes;
     const int64_t st0 = uniform64(sd->state[0]), st1 = uniform64(sd->state[1]);
     const S* pre = reinterpret_cast<const S*>(a.base + (a.parity ? st1 : st0));
     S* post = reinterpret_cast<S*>(a.base + (a.parity ? st0 : st1));
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
-        it.pre[c] = make_rsrc(pre + c * stride, abytes);
-        it.post[c] = make_rsrc(post + c * stride, abytes);
+        it.pre[c] = make_rsrc(pre + c * stride, zr_packed(G, MODE) ? 4 * abytes : abytes);
+        it.post[c] = make_rsrc(post + c * stride, zr_packed(G, MODE) ? 4 * abytes : abytes);
     }
     it.xm = make_rsrc(a.base + uniform64(sd->xmask),
                       (uint32_t)(((int64_t)it.xw * it.ny * it.nz + 2) * 4));
@@ -995,8 +1009,8 @@ __device__ __forceinline__ void zr_item(const StepArgs& a, const SampleDev* sd, 
     wp.cur0 = wp.cur1 = 0;
     wp.cur = 0;
     wall_offsets(it, z0, wp.next0, wp.next1);
-    // row requested ahead for the first source plane: the own row (shared
-    // rows) or row y-1 (rolling prefetch)
+    // own row of the first source plane, requested ahead (shared rows and
+    // rolling prefetch)
     RawRow<PX> rm;
     PkPipe<C> pk;
     if constexpr (zr_packed(G, MODE)) {
@@ -1006,11 +1020,13 @@ __device__ __forceinline__ void zr_item(const StepArgs& a, const SampleDev* sd, 
         chunk_voffs(it, t, pk.vcur);
 #pragma unroll
         for (int c = 0; c < C; ++c) pk.vst[c] = kOob;  // plane z0 - 2 is not stored
-        row_tab(it, zp + it.ym, pk.em);
-        row_tab(it, zp + it.yp, pk.ep);
+        row_tab(it, zp + it.ym, t);
+        chunk_voffs(it, t, pk.vm);
+        row_tab(it, zp + it.yp, t);
+        chunk_voffs(it, t, pk.vp);
         load_row_pk(it, pk.vcur, rm);
     } else if constexpr (MODE != 0) {
-        load_row(it, wrapi((z0 - 1) % it.nz, it.nz) * it.ny + (zr_share(G, MODE) ? it.yc : it.ym), rm);
+        load_row(it, wrapi((z0 - 1) % it.nz, it.nz) * it.ny + it.yc, rm);
     }
     int zs = z0 - 1;
     while (true) {
@@ -1027,13 +1043,17 @@ __device__ __forceinline__ void zr_item(const StepArgs& a, const SampleDev* sd, 
 }
 
 // Work item (4 x int32): sample, row group, z-segment start, z-segment end.
+// Shared-row instances target two waves per SIMD (at most 256 registers per
+// lane): the row slots of two workgroups fill a CU's LDS.
 // Workgroups are remapped so that each XCD walks a contiguous range of items
 // (neighbouring rows share their y-1 / y+1 reads in that XCD's L2).  Each
 // instance compiles one lane layout V (its register budget alone sets the
 // occupancy); batches of differently sized samples launch one instance per
 // layout present.
 template <int Q, int P, int V, int MODE>
-__global__ __launch_bounds__(kZrThreads) void k_zmarch(StepArgs a) {
+__global__ __launch_bounds__(kZrThreads)
+__attribute__((amdgpu_waves_per_eu(zr_share(kVariants[V].g, MODE) ? 2 : 1)))
+void k_zmarch(StepArgs a) {
     static_assert(V >= 0 && V < kNumVariants, "one lane layout per instance");
     constexpr int G = kVariants[V].g, C = kVariants[V].c, K = kVariants[V].k;
     constexpr int kPX = C * K;

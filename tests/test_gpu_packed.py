@@ -158,3 +158,26 @@ def test_padding_rows_ignore_workspace_contents(tile, layout):
     eps = 2.0 ** -24
     assert err["u_rel_l2"] <= 8.0 * eps
     sim.close()
+
+
+def test_dense_one_row_layout_in_packed_context():
+    """A one-row layout too large to pack (here nx = 512 with 4 * 136M * 4 B
+    of state per buffer) runs the dense shared-row schedule next to a packed
+    layout of the same context; both match their solo runs bit for bit."""
+    big = np.zeros((520, 512, 512), np.uint8)
+    small, ds_, us_ = state(512, 3, 5, seed=8700)
+    other, do_, uo_ = state(256, 6, 5, seed=8701)
+    g = (1e-5, 2e-6, 0.0)
+    print("[case] dense one-row layout in a packed context", flush=True)
+    sim = tau1.Sim([tau1.Sample(big), tau1.Sample(small, ds_, us_), tau1.Sample(other, do_, uo_)],
+                   lattice=19, precision="f32", g=g, kernel=1, tile=13, layout=1)
+    assert sim.info()["layout"] == 1
+    sim.step(4)
+    got_small, got_other = sim.moments(1), sim.moments(2)
+    sim.close()
+    solo_s, o_s = run([(small, ds_, us_)], 19, "f32", g, 4, tile=5, layout=0)
+    solo_o, o_o = run([(other, do_, uo_)], 19, "f32", g, 4, tile=13, layout=1)
+    assert_same(got_small, o_s[0], "dense 512 row layout")
+    assert_same(got_other, o_o[0], "packed 256 row layout")
+    solo_s.close()
+    solo_o.close()

@@ -95,3 +95,19 @@ def test_bad_layout_rejected(lib, layout):
                          layout)
     n = ctypes.c_size_t(0)
     assert lib.tau1_workspace_size(ctypes.byref(d), ctypes.byref(n)) == tau1.TAU1_E_INVALID
+
+
+def test_oversized_layout_stays_dense(lib):
+    """A lane layout is packed only if every sample of it fits 32-bit offsets
+    over its four packed arrays; the other layouts of the context still pack."""
+    big = np.zeros((520, 512, 512), np.uint8)       # 4 * 136M * 4 B > 2 GiB
+    small = inputs.random_state(512, 3, 5, seed=9200, solid_frac=0.7)[0]
+    other = inputs.random_state(256, 6, 5, seed=9201, solid_frac=0.7)[0]
+    with pytest.raises(tau1.Tau1Error):
+        tau1.workspace_size([(big,), (small,)], layout=1)
+    dense = tau1.workspace_size([(big,), (small,), (other,)], layout=0)
+    packed = tau1.workspace_size([(big,), (small,), (other,)], layout=1)
+    k, groups = G1[256]
+    ds = align(other.size * 4) // 4
+    ps = align(fluid_chunks(other, k) * k * 4) // 4
+    assert packed == dense - 2 * (align(4 * ds * 4) - align(4 * ps * 4)) + align(16 * 6 * 5 * groups)
