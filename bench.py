@@ -22,6 +22,11 @@ Sections (``--sections``, default all):
              radius U[4, 16], seeds 5000+i) in one launch per step, 100-step
              graphs, autotuned tiles, 1000 steps; against the same samples run
              one by one.
+  porosity   D3Q19 FP32 on 256^3 sphere packings (r = 8, target porosity 0.5,
+             0.6, 0.7, 0.8, 0.9, seeds 2000+i), 1000 steps each, packed and
+             dense state layouts, permeability, and the chunk statistics of the
+             paper's bandwidth model for porous media (fraction of lane chunks
+             stored, mean porosity of the stored chunks, share of mixed chunks).
 The oracle leg (``cpu_baseline``) times the FP64 CPU oracle on a few steps of
 the main workload on the host cores.
 
@@ -44,6 +49,7 @@ if ROOT not in sys.path:
 METRIC = "Tau1 D3Q19 GFLUPS + % HBM roofline: FP32 vs 16-bit storage vs batched"
 PEAK_HBM_GBS = 8000.0          # MI355X HBM3E, published
 G_MAIN = (1e-6, 0.0, 0.0)
+POROSITIES = (0.5, 0.6, 0.7, 0.8, 0.9)
 COUNTERS = os.path.join(ROOT, "profiles", "zmarch_d3q19_f32_512cube_phi07.counters.txt")
 KERNEL_SOURCES = ("tau1_device.hpp", "tau1_kernels.hpp", "tau1_zmarch.hpp",
                   "tau1_zmarch_inst.hip")
@@ -58,12 +64,13 @@ def parse_args(argv=None):
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=500, help="timed steps of the main workload")
     ap.add_argument("--warmup", type=int, default=100, help="untimed steps before timing")
-    ap.add_argument("--sections", default="main,lattices,precision,batch")
+    ap.add_argument("--sections", default="main,lattices,precision,batch,porosity")
     ap.add_argument("--tile", type=int, default=-1, help="z-march tile; -1 = autotune")
     ap.add_argument("--graph-chunk", type=int, default=100)
     ap.add_argument("--lattice-steps", type=int, default=500)
     ap.add_argument("--precision-steps", type=int, default=2000)
     ap.add_argument("--batch-steps", type=int, default=1000)
+    ap.add_argument("--porosity-steps", type=int, default=1000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--oracle-accuracy", action="store_true",
                     help="also compare the 128^3 crop with the FP64 oracle (slow)")
@@ -110,6 +117,12 @@ def gen_inputs(args, sections):
         geos["prec"] = inputs.spheres(512, 512, 512, 12.0, 0.6, seed=4000)
         log(f"precision geometry: porosity {geos['prec'].porosity:.5f} "
             f"({time.perf_counter() - t:.1f} s)")
+    if "porosity" in sections:
+        t = time.perf_counter()
+        geos["poro"] = [inputs.spheres(256, 256, 256, 8.0, phi, seed=2000 + i)
+                        for i, phi in enumerate(POROSITIES)]
+        log(f"porosity sweep geometries: {[round(g.porosity, 4) for g in geos['poro']]} "
+            f"({time.perf_counter() - t:.1f} s)")
     if "batch" in sections:
         t = time.perf_counter()
         workers = max(1, min(16, os.cpu_count() or 1))
@@ -151,10 +164,10 @@ class GpuRunner:
         torch.cuda.set_device(self.device)
 
     def make(self, samples, lattice, precision, g, graph_chunk, tile, kernel=-1,
-             f16_scales=(0, 0)):
+             f16_scales=(0, 0), layout=-1):
         sim = self.tau1.Sim(samples, lattice=lattice, precision=precision, g=g,
                             graph_chunk=graph_chunk, kernel=kernel, tile=tile,
-                            f16_scales=f16_scales)
+                            f16_scales=f16_scales, layout=layout)
         if tile < 0 and kernel != 0:
             sim.autotune(10)
         return sim
@@ -178,8 +191,8 @@ class GpuRunner:
         return wall, ev
 
     def case(self, samples, lattice, precision, steps, warmup, graph_chunk, tile,
-             g=G_MAIN, label=""):
-        sim = self.make(samples, lattice, precision, g, graph_chunk, tile)
+             g=G_MAIN, label="", layout=-1):
+        sim = self.make(samples, lattice, precision, g, graph_chunk, tile, layout=layout)
         wall, ev = self.time_steps(sim, steps, warmup)
         inf = sim.info()
         res = {
@@ -187,7 +200,7 @@ class GpuRunner:
             "ms_per_step": wall / steps * 1e3,
             "launch_ms": ev / steps * 1e3,
             "alg_gbs": inf["bytes_per_step"] / (ev / steps) / 1e9,
-            "tile": inf["tile"], "kernel": inf["kernel"],
+            "tile": inf["tile"], "kernel": inf["kernel"], "layout": inf["layout"],
             "n_fluid": inf["n_fluid"], "n_nodes": inf["n_nodes"],
             "bytes_per_step": inf["bytes_per_step"],
         }
@@ -302,6 +315,60 @@ def batch_section(gr, batch, args, out):
     out["batched"] = res
 
 
+# D3Q19 directions without the rest one (chunk statistics below)
+D3Q19_DIRS = [(1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, -1, 0), (0, 0, 1), (0, 0, -1),
+              (1, 1, 0), (-1, -1, 0), (1, -1, 0), (-1, 1, 0), (1, 0, 1), (-1, 0, -1),
+              (1, 0, -1), (-1, 0, 1), (0, 1, 1), (0, -1, -1), (0, 1, -1), (0, -1, 1)]
+
+
+def chunk_stats(solid, k):
+    """Chunk statistics of the paper's bandwidth model for porous media, for
+    chunks of k consecutive x-nodes: the share of chunks holding a fluid node
+    (the ones the packed layout stores), the mean porosity of those chunks
+    (phi_chunk) and the share of them that are mixed (R_mixed: a solid node,
+    or a node with a solid D3Q19 neighbour, periodic)."""
+    import numpy as np
+    fl = solid == 0
+    nz, ny, nx = fl.shape
+    stored = fl.reshape(nz, ny, nx // k, k).any(-1)
+    clear = fl.copy()
+    for cx, cy, cz in D3Q19_DIRS:
+        clear &= np.roll(fl, shift=(-cz, -cy, -cx), axis=(0, 1, 2))
+    pure = clear.reshape(nz, ny, nx // k, k).all(-1)
+    n_st = int(stored.sum())
+    return {"chunk_nodes": k, "stored_chunk_frac": n_st / stored.size,
+            "phi_chunk": float(fl.sum()) / max(n_st * k, 1),
+            "r_mixed": float((stored & ~pure).sum()) / max(n_st, 1)}
+
+
+def porosity_section(gr, geos, args, out):
+    from paper_2312_14742_amd import tau1
+    rows = []
+    for phi, geo in zip(POROSITIES, geos):
+        row = {"target": phi, "porosity": geo.porosity, "spheres": geo.spheres}
+        for layout, name in ((1, "packed"), (0, "dense")):
+            sim, res = gr.case([tau1.Sample(geo.solid)], 19, "f32", args.porosity_steps,
+                               args.warmup, args.graph_chunk, -1,
+                               label=f"porosity {phi} {name}", layout=layout)
+            if layout == 1:
+                row["k"], row["mass"] = sim.permeability(0, 0)
+            sim.close()
+            row[name] = {key: res[key] for key in ("gflups", "alg_gbs", "frac", "tile",
+                                                   "launch_ms")}
+        row.update(chunk_stats(geo.solid, 4))
+        # bytes the packed layout moves per step: state of the stored chunks read
+        # and written once, as a rate over the measured launch time
+        moved = 2 * 16 * row["stored_chunk_frac"] * geo.solid.size
+        row["packed"]["stored_gbs"] = moved / (row["packed"]["launch_ms"] * 1e-3) / 1e9
+        rows.append(row)
+    out["porosity_sweep"] = {
+        "workload": "D3Q19 FP32, 256^3 periodic sphere packings, r=8, target porosity "
+                    "0.5..0.9, seeds 2000+i, g=1e-6 x, "
+                    f"{args.porosity_steps} steps per case; the working set (0.3-0.5 GB "
+                    "packed) is of the order of the 256 MB last-level cache",
+        "cases": rows}
+
+
 def main(argv=None):
     args = parse_args(argv)
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -352,6 +419,8 @@ def main(argv=None):
         precision_section(gr, geos["prec"], args, out)
     if "batch" in sections:
         batch_section(gr, geos["batch"], args, out)
+    if "porosity" in sections:
+        porosity_section(gr, geos["poro"], args, out)
 
     line = {"metric": METRIC, "higher_is_better": True, "n_gpus": 1, "scaling": "weak",
             "vs_baseline": None, "dtype": "f32", "data": "synthetic",

@@ -52,3 +52,39 @@ def reduced_errors(gpu, ref, solid):
         "u_rel_l2": float(rel_l2(u, ref.u, fl)),
         "u_max_rel": float(np.abs(u - ref.u).max() / max(np.abs(ref.u).max(), 1e-300)),
     }
+
+
+# Unit roundoff of the storage formats of the reduced-precision modes.
+UNIT_ROUNDOFF = {"f32": 2.0 ** -24, "f16": 2.0 ** -11, "bf16": 2.0 ** -8}
+
+
+def sample_nodes(solid, n_random, seed):
+    """Random fluid nodes plus whole rows and planes at the periodic edges."""
+    nz, ny, nx = solid.shape
+    rng = np.random.Generator(np.random.PCG64(seed))
+    fluid = np.flatnonzero(solid.ravel() == 0)
+    idx = [rng.choice(fluid, size=min(n_random, fluid.size), replace=False)]
+    for (y, z) in [(0, 0), (ny - 1, nz - 1), (ny // 2, 0), (0, nz // 2), (ny - 1, 1)]:
+        idx.append(np.arange(nx) + nx * (y + ny * z))
+    for x in (0, nx - 1):
+        yy, zz = np.meshgrid(np.arange(0, ny, 7), np.arange(0, nz, 7), indexing="ij")
+        idx.append((x + nx * (yy + ny * zz)).ravel())
+    idx = np.unique(np.concatenate(idx))
+    return idx[solid.ravel()[idx] == 0]
+
+
+def check_step(sim, sample, solid, q, prec, g, idx, label):
+    d0, u0 = sim.moments(sample)
+    sim.step(1)
+    d1, u1 = sim.moments(sample)
+    ref = oracle.step_nodes(q, oracle.State(solid, d0, u0), g, idx)
+    got_d = d1.ravel()[idx]
+    got_u = np.stack([u1[a].ravel()[idx] for a in range(3)], axis=1)
+    eps = UNIT_ROUNDOFF[prec]
+    umax = np.abs(ref[:, 1:]).max()
+    ed = np.abs(got_d - ref[:, 0]).max()
+    eu = np.sqrt(np.sum((got_u - ref[:, 1:]) ** 2) / np.sum(ref[:, 1:] ** 2))
+    print(f"[err] {label}: {idx.size} nodes, max|ddrho| {ed:.3e}, rel-L2(u) {eu:.3e}, "
+          f"max|u| {umax:.3e}", flush=True)
+    assert ed <= (2.0 * eps + 16.0 * 2.0 ** -24) * umax, (label, ed)
+    assert eu <= 8.0 * eps, (label, eu)

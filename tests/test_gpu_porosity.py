@@ -1,0 +1,58 @@
+"""Porosity sweep: D3Q19 FP32 on 256^3 periodic sphere packings (r = 8,
+target porosity 0.5 ... 0.9, seeds 2000 + i), body force 1e-6 along x,
+1000 steps, permeability reported.
+
+The oracle cannot run 1000 steps of 256^3, so each porosity checks:
+- the 1000th step at sampled nodes against the oracle's single-node update of
+  the GPU state after 999 steps (same bounds as the other full-size cases);
+- the FP32 permeability against the library's FP64 mode (itself within 1e-12
+  of the oracle on the small cases) on the same input, within
+  1000 steps x 2 x 2^-24 relative, FP32 rounding growing at most linearly;
+- mass conservation: sum of rho over the fluid nodes stays N_f to 1e-9;
+and across the sweep the permeability must grow with the porosity."""
+import numpy as np
+import pytest
+
+from paper_2312_14742_amd import inputs, tau1
+
+from gpu_helpers import check_step, sample_nodes
+
+pytestmark = pytest.mark.gpu
+
+PHIS = [0.5, 0.6, 0.7, 0.8, 0.9]
+STEPS = 1000
+G = (1e-6, 0.0, 0.0)
+_K = {}
+
+
+@pytest.mark.parametrize("i,phi", list(enumerate(PHIS)))
+def test_porosity_sweep_256(i, phi):
+    geo = inputs.spheres(256, 256, 256, 8.0, phi, seed=2000 + i)
+    nf = geo.n_fluid
+    print(f"[case] 256^3 r=8 target porosity {phi} (achieved {geo.porosity:.4f})", flush=True)
+    with tau1.Sim([tau1.Sample(geo.solid)], lattice=19, precision="f32", g=G,
+                  graph_chunk=100) as sim:
+        sim.autotune(3)
+        sim.step(STEPS - 1)
+        idx = sample_nodes(geo.solid, 20000, seed=i)
+        check_step(sim, 0, geo.solid, 19, "f32", G, idx, f"porosity {phi}")
+        k32, m32 = sim.permeability(0, 0)
+        layout = sim.info()["layout"]
+    with tau1.Sim([tau1.Sample(geo.solid)], lattice=19, precision="f64", g=G,
+                  graph_chunk=100) as ref:
+        ref.step(STEPS)
+        k64, m64 = ref.permeability(0, 0)
+    print(f"[err] porosity {phi}: layout {layout}, k32 {k32:.9e} k64 {k64:.9e} "
+          f"rel {abs(k32 - k64) / k64:.2e}, mass32-Nf {m32 - nf:.3e}", flush=True)
+    assert layout == 1
+    assert abs(k32 - k64) <= STEPS * 2.0 * 2.0 ** -24 * abs(k64)
+    assert abs(m32 - nf) <= 1e-9 * nf
+    assert abs(m64 - nf) <= 1e-12 * nf
+    _K[phi] = k64
+
+
+def test_permeability_grows_with_porosity():
+    if len(_K) != len(PHIS):
+        pytest.skip("needs every porosity of the sweep")
+    ks = [_K[p] for p in PHIS]
+    assert all(a < b for a, b in zip(ks, ks[1:])), ks
