@@ -22,11 +22,12 @@ Sections (``--sections``, default all):
              radius U[4, 16], seeds 5000+i) in one launch per step, 100-step
              graphs, autotuned tiles, 1000 steps; against the same samples run
              one by one.
-  porosity   D3Q19 FP32 on 256^3 sphere packings (r = 8, target porosity 0.5,
-             0.6, 0.7, 0.8, 0.9, seeds 2000+i), 1000 steps each, packed and
-             dense state layouts, permeability, and the chunk statistics of the
-             paper's bandwidth model for porous media (fraction of lane chunks
-             stored, mean porosity of the stored chunks, share of mixed chunks).
+  porosity   D3Q19 FP32 on 256^3 sphere packings (r = 8, target porosity 0.05,
+             0.1, 0.2, 0.3, 0.5, 0.6, 0.7, 0.8, 0.9, seeds 2000+i), 1000 steps
+             each, packed and dense state layouts, permeability, work items
+             visited, and the chunk statistics of the paper's bandwidth model
+             for porous media (fraction of lane chunks stored, mean porosity of
+             the stored chunks, share of mixed chunks).
 The oracle leg (``cpu_baseline``) times the FP64 CPU oracle on a few steps of
 the main workload on the host cores.
 
@@ -49,7 +50,7 @@ if ROOT not in sys.path:
 METRIC = "Tau1 D3Q19 GFLUPS + % HBM roofline: FP32 vs 16-bit storage vs batched"
 PEAK_HBM_GBS = 8000.0          # MI355X HBM3E, published
 G_MAIN = (1e-6, 0.0, 0.0)
-POROSITIES = (0.5, 0.6, 0.7, 0.8, 0.9)
+POROSITIES = (0.05, 0.1, 0.2, 0.3, 0.5, 0.6, 0.7, 0.8, 0.9)
 COUNTERS = os.path.join(ROOT, "profiles", "zmarch_d3q19_f32_512cube_phi07.counters.txt")
 KERNEL_SOURCES = ("tau1_device.hpp", "tau1_kernels.hpp", "tau1_zmarch.hpp",
                   "tau1_zmarch_inst.hip")
@@ -201,6 +202,7 @@ class GpuRunner:
             "launch_ms": ev / steps * 1e3,
             "alg_gbs": inf["bytes_per_step"] / (ev / steps) / 1e9,
             "tile": inf["tile"], "kernel": inf["kernel"], "layout": inf["layout"],
+            "work_items": inf["work_items"],
             "n_fluid": inf["n_fluid"], "n_nodes": inf["n_nodes"],
             "bytes_per_step": inf["bytes_per_step"],
         }
@@ -354,7 +356,7 @@ def porosity_section(gr, geos, args, out):
                 row["k"], row["mass"] = sim.permeability(0, 0)
             sim.close()
             row[name] = {key: res[key] for key in ("gflups", "alg_gbs", "frac", "tile",
-                                                   "launch_ms")}
+                                                   "launch_ms", "work_items")}
         row.update(chunk_stats(geo.solid, 4))
         # bytes the packed layout moves per step: state of the stored chunks read
         # and written once, as a rate over the measured launch time
@@ -363,7 +365,7 @@ def porosity_section(gr, geos, args, out):
         rows.append(row)
     out["porosity_sweep"] = {
         "workload": "D3Q19 FP32, 256^3 periodic sphere packings, r=8, target porosity "
-                    "0.5..0.9, seeds 2000+i, g=1e-6 x, "
+                    "0.05..0.9, seeds 2000+i, g=1e-6 x, "
                     f"{args.porosity_steps} steps per case; the working set (0.3-0.5 GB "
                     "packed) is of the order of the 256 MB last-level cache",
         "cases": rows}

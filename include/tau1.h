@@ -128,6 +128,9 @@ typedef struct {
     double bytes_per_step;   /* algorithmic HBM bytes of one step (all samples):
                                 2 (d+1) s per fluid node plus one mask bit per
                                 node (complexity table of the paper)        */
+    int64_t work_items;      /* z-march work items per step (row groups x
+                                z-segments holding a fluid node), 0 for the
+                                gather kernel                               */
 } tau1_info;
 
 /* Bytes of device workspace the descriptor needs.  Host only, no GPU call. */

@@ -32,6 +32,7 @@ struct SampleHost {
     SampleDev dev;
     int64_t n_fluid;
     std::vector<uint32_t> ctab;  // packed layout: chunk table (4 words per entry)
+    std::vector<uint8_t> rowfluid;  // z-march samples: 1 if row y + ny z holds a fluid node
 };
 
 // Byte layout of the workspace for one descriptor.
@@ -692,15 +693,30 @@ tau1_status tau1_create(const tau1_desc* desc, tau1_ctx** out) {
         a.scale_u = std::ldexp(1.0f, lsu);
         a.inv_scale_u = std::ldexp(1.0f, -lsu);
     }
-    // fluid counts (host marshalling of the geometry)
+    // fluid counts, and for z-march samples the rows holding a fluid node
+    // (host marshalling of the geometry)
     for (int i = 0; i < ctx->nsamples; ++i) {
         const tau1_sample& s = desc->samples[i];
-        const int64_t n = s.nx * s.ny * s.nz;
+        const int64_t rows = s.ny * s.nz;
+        SampleHost& sh = ctx->plan.s[i];
+        const bool rowflags = sh.dev.variant >= 0;
+        try {
+            if (rowflags) sh.rowfluid.assign((size_t)rows, 0);
+        } catch (const std::bad_alloc&) {
+            delete ctx;
+            return TAU1_E_NOMEM;
+        }
         int64_t nf = 0;
-        for (int64_t j = 0; j < n; ++j) nf += s.solid[j] ? 0 : 1;
-        ctx->plan.s[i].n_fluid = nf;
+        for (int64_t r = 0; r < rows; ++r) {
+            const uint8_t* row = s.solid + r * s.nx;
+            int64_t c = 0;
+            for (int64_t x = 0; x < s.nx; ++x) c += row[x] ? 0 : 1;
+            nf += c;
+            if (rowflags) sh.rowfluid[(size_t)r] = c != 0;
+        }
+        sh.n_fluid = nf;
         ctx->n_fluid += nf;
-        ctx->n_nodes += n;
+        ctx->n_nodes += rows * s.nx;
     }
     // descriptors
     std::vector<SampleDev> sdev(ctx->nsamples);
@@ -871,6 +887,10 @@ tau1_status tau1_get_info(const tau1_ctx* ctx, tau1_info* info) {
     info->steps_done = ctx->steps_done;
     const double s = storage_bytes(ctx->precision);
     info->bytes_per_step = 2.0 * 4.0 * s * (double)ctx->n_fluid + (double)ctx->n_nodes / 8.0;
+    int64_t items = 0;
+    if (ctx->kernel == 1)
+        for (const auto& g : ctx->zgroups) items += g.args[0].ntiles;
+    info->work_items = items;
     return TAU1_OK;
 }
 

@@ -35,6 +35,7 @@
 // two scaled) or BF16.
 #pragma once
 
+#include <algorithm>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -1173,7 +1174,12 @@ inline int zmarch_rows(const SampleDev& sd, bool blocks) {
 
 // Work list of the samples with lane layout `variant`, for z-segment length
 // lz: items (sample, row group, z0, z1) with row groups fastest so
-// neighbouring rows are neighbouring items.
+// neighbouring rows are neighbouring items.  Only items with a fluid node in
+// their rows and planes are listed (`s[i].rowfluid`, one flag per row
+// y + ny z, when present): the others would store nothing, and their rows'
+// state is read from memory by the items next to them.  With shared rows
+// (`blocks`) a block of kZrWaves row items is kept or dropped as a whole, so
+// the waves of a workgroup still march the same z-segment.
 template <typename SH>
 inline std::vector<int32_t> zmarch_worklist(const SH* s, int n, int lz, int variant, bool blocks) {
     std::vector<int32_t> out;
@@ -1181,13 +1187,23 @@ inline std::vector<int32_t> zmarch_worklist(const SH* s, int n, int lz, int vari
         const SampleDev& sd = s[i].dev;
         if (sd.variant < 0 || sd.variant != variant) continue;
         const int rows = zmarch_rows(sd, blocks);
+        const int g = kVariants[sd.variant].g;
+        const int step = blocks && g == 1 ? kZrWaves : 1;  // row items kept together
+        const auto& rf = s[i].rowfluid;
         for (int z0 = 0; z0 < sd.nz; z0 += lz) {
             const int z1 = z0 + lz < sd.nz ? z0 + lz : sd.nz;
-            for (int rg = 0; rg < rows; ++rg) {
-                out.push_back(i);
-                out.push_back(rg);
-                out.push_back(z0);
-                out.push_back(z1);
+            for (int rg0 = 0; rg0 < rows; rg0 += step) {
+                bool busy = rf.empty();
+                const int y0 = rg0 * g, y1 = std::min((rg0 + step) * g, sd.ny);
+                for (int z = z0; z < z1 && !busy; ++z)
+                    for (int y = y0; y < y1 && !busy; ++y) busy = rf[(size_t)z * sd.ny + y] != 0;
+                if (!busy) continue;
+                for (int rg = rg0; rg < rg0 + step; ++rg) {
+                    out.push_back(i);
+                    out.push_back(rg);
+                    out.push_back(z0);
+                    out.push_back(z1);
+                }
             }
         }
     }

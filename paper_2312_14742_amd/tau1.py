@@ -66,7 +66,8 @@ class tau1_info(ctypes.Structure):
                 ("tile", ctypes.c_int32), ("graph_chunk", ctypes.c_int32),
                 ("layout", ctypes.c_int32),
                 ("n_nodes", ctypes.c_int64), ("n_fluid", ctypes.c_int64),
-                ("steps_done", ctypes.c_int64), ("bytes_per_step", ctypes.c_double)]
+                ("steps_done", ctypes.c_int64), ("bytes_per_step", ctypes.c_double),
+                ("work_items", ctypes.c_int64)]
 
 
 _LIB = None

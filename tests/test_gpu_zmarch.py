@@ -214,3 +214,48 @@ def test_autotune_keeps_state_and_uses_cache(tmp_path):
                      tune_cache=cache)
     assert again.info()["tile"] == tuned
     again.close()
+
+
+def expected_items(solid, lz, block):
+    """Work items (row item x z-segment) holding a fluid node; shared-row
+    tiles keep or drop blocks of four row items."""
+    nz, ny, nx = solid.shape
+    rowf = (solid == 0).any(axis=2)
+    step = 4 if block else 1
+    rows = (ny + 3) // 4 * 4 if block else ny
+    n = 0
+    for z0 in range(0, nz, lz):
+        for r0 in range(0, rows, step):
+            if rowf[z0:z0 + lz, r0:min(r0 + step, ny)].any():
+                n += step
+    return n
+
+
+def test_all_solid_regions_are_skipped():
+    """Row groups and z-segments without a fluid node are not visited; every
+    tile still gives the oracle's result and the same bits."""
+    nx, ny, nz = 64, 12, 48
+    solid, drho, u = inputs.random_state(nx, ny, nz, seed=8800)
+    solid[:32] = 1          # planes 0-31 solid
+    solid[:, 4:8] = 1       # rows 4-7 solid in every plane
+    drho[solid == 1] = 0.0
+    u[:, solid == 1] = 0.0
+    g = (1e-5, -2e-5, 3e-6)
+    ref = run_oracle(19, solid, drho, u, g, 6)
+    outs = []
+    for tile in (0, 2, 4, 6, 8, 12, 14):
+        print(f"[case] solid regions, tile {tile}", flush=True)
+        sim, out = run_gpu([(solid, drho, u)], 19, "f32", g, 6, kernel=1, tile=tile,
+                           layout=1 if tile >= 12 else 0)
+        lz = (16, 32, 64, 128)[tile % 4]
+        block = tile // 4 in (1, 3)
+        assert sim.info()["work_items"] == expected_items(solid, lz, block), tile
+        assert expected_items(solid, lz, block) < expected_items(np.zeros_like(solid), lz, block)
+        err = reduced_errors(out[0], ref, solid)
+        for key, b in bounds("f32", np.abs(u).max()).items():
+            assert err[key] <= b, (tile, key, err[key], b)
+        outs.append(out[0])
+        sim.close()
+    for o in outs[1:]:
+        assert o[0].tobytes() == outs[0][0].tobytes()
+        assert o[1].tobytes() == outs[0][1].tobytes()
