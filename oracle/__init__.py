@@ -14,6 +14,11 @@ Functions follow the paper's statement of the method:
   as printed.
 * :func:`step_nodes` -- one update at chosen nodes from a full state.
 * :func:`reduce` -- mass and Darcy permeability.
+
+Two-dimensional validation lattice (``tau1_oracle_2d.c``, a library of its
+own): :func:`run_2d` (D2Q9 Tau1 with walls, moving walls and Zou-He pressure
+columns), :func:`bgk_run_2d` (its brute-force population counterpart),
+:func:`reduce_2d`, :func:`lattice_2d`.
 """
 from __future__ import annotations
 
@@ -26,17 +31,20 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "tau1_oracle.c")
 _LIB = os.path.join(_HERE, "libtau1_oracle.so")
+_SRC2D = os.path.join(_HERE, "tau1_oracle_2d.c")
+_LIB2D = os.path.join(_HERE, "libtau1_oracle_2d.so")
 
 CFLAGS = ["-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
           "-std=c99", "-Wall", "-Wextra", "-shared", "-fPIC"]
 
 
 def build(force: bool = True) -> str:
-    """Compile the oracle with gcc; returns the library path."""
-    if force or not os.path.exists(_LIB):
-        tmp = _LIB + ".tmp"
-        subprocess.run(["gcc", *CFLAGS, _SRC, "-o", tmp, "-lm"], check=True)
-        os.replace(tmp, _LIB)
+    """Compile the oracle libraries with gcc; returns the 3-D library path."""
+    for src, lib in ((_SRC, _LIB), (_SRC2D, _LIB2D)):
+        if force or not os.path.exists(lib):
+            tmp = lib + ".tmp"
+            subprocess.run(["gcc", *CFLAGS, src, "-o", tmp, "-lm"], check=True)
+            os.replace(tmp, lib)
     return _LIB
 
 
@@ -214,3 +222,100 @@ def reduce(st: State, axis: int, g_axis: float):
     if rc != 0:
         raise RuntimeError("tau1o_reduce failed")
     return float(m[0]), float(k[0])
+
+
+# ---------------------------------------------------------------------------
+# Two-dimensional validation lattice (D2Q9)
+# ---------------------------------------------------------------------------
+_lib2d = None
+
+
+def _load2d():
+    global _lib2d
+    if _lib2d is None:
+        if not os.path.exists(_LIB2D):
+            build(force=True)
+        lib = ctypes.CDLL(_LIB2D)
+        P, L, I, D = ctypes.c_void_p, ctypes.c_long, ctypes.c_int, ctypes.c_double
+        lib.tau1o2_lattice.argtypes = [P, P, P]
+        lib.tau1o2_run.argtypes = [L, L, P, P, P, P, P, P, I, D, D, L, I]
+        lib.tau1o2_bgk_run.argtypes = [L, L, P, P, P, P, P, P, I, D, D, D, L]
+        lib.tau1o2_reduce.argtypes = [L, L, P, P, P, P, P]
+        _lib2d = lib
+    return _lib2d
+
+
+def lattice_2d():
+    """D2Q9 direction vectors (9 x 2), weights and opposite map."""
+    c = np.zeros((9, 2), dtype=np.int32)
+    w = np.zeros(9, dtype=np.float64)
+    opp = np.zeros(9, dtype=np.int32)
+    _load2d().tau1o2_lattice(_ptr(c), _ptr(w), _ptr(opp))
+    return c, w, opp
+
+
+class State2D:
+    """Node types (0 fluid, 1 wall, 2 moving wall), drho = rho - 1 and
+    velocity (ux, uy), FP64, arrays of shape (ny, nx) (x fastest)."""
+
+    def __init__(self, types: np.ndarray, drho=None, u=None):
+        types = np.ascontiguousarray(types, dtype=np.uint8)
+        if types.ndim != 2:
+            raise ValueError("types must be (ny, nx)")
+        self.types = types
+        self.drho = (np.zeros(types.shape) if drho is None
+                     else np.array(drho, dtype=np.float64, copy=True).reshape(types.shape))
+        self.u = (np.zeros((2,) + types.shape) if u is None
+                  else np.array(u, dtype=np.float64, copy=True).reshape((2,) + types.shape))
+
+    def copy(self):
+        return State2D(self.types, self.drho, self.u)
+
+
+def _bc_args(g, uw, xbc, rho_in, rho_out):
+    return (np.array(g, dtype=np.float64), np.array(uw, dtype=np.float64), int(xbc),
+            float(rho_in), float(rho_out))
+
+
+def run_2d(st: State2D, nsteps: int, g=(0.0, 0.0), uw=(0.0, 0.0), xbc=0, rho_in=1.0,
+           rho_out=1.0, nthreads: int = 0) -> State2D:
+    """nsteps D2Q9 Tau1 updates of a copy of st (walls, moving walls with
+    velocity uw, Zou-He pressure columns at x = 0 and nx - 1 when xbc = 1)."""
+    out = st.copy()
+    ny, nx = st.types.shape
+    ga, ua, xb, ri, ro = _bc_args(g, uw, xbc, rho_in, rho_out)
+    ux = np.ascontiguousarray(out.u[0])
+    uy = np.ascontiguousarray(out.u[1])
+    rc = _load2d().tau1o2_run(nx, ny, _ptr(out.types), _ptr(out.drho), _ptr(ux), _ptr(uy),
+                              _ptr(ga), _ptr(ua), xb, ri, ro, int(nsteps), int(nthreads))
+    if rc != 0:
+        raise RuntimeError(f"tau1o2_run failed ({rc})")
+    out.u = np.stack([ux, uy])
+    return out
+
+
+def bgk_run_2d(st: State2D, nsteps: int, omega: float = 1.0, g=(0.0, 0.0), uw=(0.0, 0.0),
+               xbc=0, rho_in=1.0, rho_out=1.0) -> State2D:
+    """Brute-force D2Q9 LBGK with full populations and the same boundary rules."""
+    out = st.copy()
+    ny, nx = st.types.shape
+    ga, ua, xb, ri, ro = _bc_args(g, uw, xbc, rho_in, rho_out)
+    ux = np.ascontiguousarray(out.u[0])
+    uy = np.ascontiguousarray(out.u[1])
+    rc = _load2d().tau1o2_bgk_run(nx, ny, _ptr(out.types), _ptr(out.drho), _ptr(ux),
+                                  _ptr(uy), _ptr(ga), _ptr(ua), xb, ri, ro, float(omega),
+                                  int(nsteps))
+    if rc != 0:
+        raise RuntimeError(f"tau1o2_bgk_run failed ({rc})")
+    out.u = np.stack([ux, uy])
+    return out
+
+
+def reduce_2d(st: State2D):
+    """(mass = sum of rho over fluid nodes, mean of u_x over all nodes)."""
+    ny, nx = st.types.shape
+    m = np.zeros(1)
+    s = np.zeros(1)
+    ux = np.ascontiguousarray(st.u[0])
+    _load2d().tau1o2_reduce(nx, ny, _ptr(st.types), _ptr(st.drho), _ptr(ux), _ptr(m), _ptr(s))
+    return float(m[0]), float(s[0])
