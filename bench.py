@@ -22,6 +22,13 @@ Sections (``--sections``, default all):
              radius U[4, 16], seeds 5000+i) in one launch per step, 100-step
              graphs, autotuned tiles, 1000 steps; against the same samples run
              one by one.
+  validation the paper's 2-D validation runs on the D2Q9 kernel: pressure-
+             driven Poiseuille flow on 1000 x 100 (rho 1.01 / 0.99 Zou-He
+             columns, halfway walls) run to the steady state (velocity change
+             per step below 1e-8 everywhere), error against Eq. (12) at x = 500;
+             lid-driven cavity L = 160 (lid 5/12, Re = 2.5 L) run until the
+             flow rate through the vertical centre line changes by less than
+             1 % over 10000 steps.
   porosity   D3Q19 FP32 on 256^3 sphere packings (r = 8, target porosity 0.05,
              0.1, 0.2, 0.3, 0.5, 0.6, 0.7, 0.8, 0.9, seeds 2000+i), 1000 steps
              each, packed and dense state layouts, permeability, work items
@@ -65,7 +72,7 @@ def parse_args(argv=None):
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=500, help="timed steps of the main workload")
     ap.add_argument("--warmup", type=int, default=100, help="untimed steps before timing")
-    ap.add_argument("--sections", default="main,lattices,precision,batch,porosity")
+    ap.add_argument("--sections", default="main,lattices,precision,batch,porosity,validation")
     ap.add_argument("--tile", type=int, default=-1, help="z-march tile; -1 = autotune")
     ap.add_argument("--graph-chunk", type=int, default=100)
     ap.add_argument("--lattice-steps", type=int, default=500)
@@ -371,6 +378,74 @@ def porosity_section(gr, geos, args, out):
         "cases": rows}
 
 
+def validation_section(gr, out):
+    """The paper's 2-D validation runs on the D2Q9 kernel (FP64)."""
+    import numpy as np
+    from paper_2312_14742_amd import tau1
+    res = {}
+    # pressure-driven Poiseuille flow
+    nx, ny, rin, rout = 1000, 100, 1.01, 0.99
+    t = np.zeros((1, ny, nx), np.uint8)
+    t[0, 0] = 1
+    t[0, -1] = 1
+    sim = tau1.Sim([tau1.Sample(t)], lattice=9, precision="f64", graph_chunk=1000,
+                   x_boundary=1, rho_in=rin, rho_out=rout)
+    steps, chunk, change = 0, 10000, None
+    t0 = time.perf_counter()
+    while steps < 1_000_000:
+        sim.step(chunk - 1)
+        _, u0 = sim.moments(0)
+        sim.step(1)
+        d, u1 = sim.moments(0)
+        steps += chunk
+        change = float(np.abs(u1 - u0).max())
+        if change < 1e-8:
+            break
+    wall = time.perf_counter() - t0
+    xc, H = 500, ny - 2
+    y = np.arange(1, ny - 1) - 0.5
+    rho = 1.0 + d[0, 1:-1, xc].mean()
+    g = -((rout - rin) / 3.0 / (nx - 1)) / rho          # -(dp/dx)/rho, p = rho/3
+    eq12 = g / (2.0 / 6.0) * y * (H - y)
+    u = u1[0, 0, 1:-1, xc]
+    res["poiseuille"] = {
+        "grid": [nx, ny], "rho_in": rin, "rho_out": rout, "steps_to_steady": steps,
+        "last_step_change": change,
+        "mape_vs_eq12": float(np.mean(np.abs(u - eq12) / eq12)),
+        "mape_vs_eq12_plus_wall_slip": float(np.mean(np.abs(u - eq12 - g / 4) / (eq12 + g / 4))),
+        "gflups": (ny - 2) * nx * steps / wall / 1e9, "seconds": wall}
+    sim.close()
+    log(f"Poiseuille {nx}x{ny}: steady after {steps} steps, MAPE vs Eq. 12 "
+        f"{100 * res['poiseuille']['mape_vs_eq12']:.4f} %")
+    # lid-driven cavity
+    L, U = 160, 5.0 / 12.0
+    t = np.zeros((1, L, L), np.uint8)
+    t[0, 0, :] = 1
+    t[0, :, 0] = 1
+    t[0, :, -1] = 1
+    t[0, -1, :] = 2
+    sim = tau1.Sim([tau1.Sample(t)], lattice=9, precision="f64", graph_chunk=100,
+                   wall_u=(U, 0.0, 0.0))
+    hist, steps = [], 0
+    t0 = time.perf_counter()
+    while steps < 1_000_000:
+        sim.step(1000)
+        steps += 1000
+        _, u = sim.moments(0)
+        q = float(np.clip(u[0, 0, :, L // 2], 0.0, None).sum())  # forward flow rate
+        hist.append(q)
+        if len(hist) > 10 and abs(hist[-1] - hist[-11]) <= 0.01 * abs(hist[-1]):
+            break
+    wall = time.perf_counter() - t0
+    mass = sim.permeability(0, 0, with_k=False)[1]
+    res["cavity"] = {"L": L, "lid_u": U, "reynolds": U * L * 6.0, "steps": steps,
+                     "flow_rate_centre_line": hist[-1], "mass_drift": mass / (L - 2) ** 2 - 1,
+                     "gflups": (L - 2) ** 2 * steps / wall / 1e9}
+    sim.close()
+    log(f"cavity L={L}: {steps} steps, flow rate {hist[-1]:.5f}")
+    out["validation_2d"] = res
+
+
 def main(argv=None):
     args = parse_args(argv)
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -423,6 +498,8 @@ def main(argv=None):
         batch_section(gr, geos["batch"], args, out)
     if "porosity" in sections:
         porosity_section(gr, geos["poro"], args, out)
+    if "validation" in sections:
+        validation_section(gr, out)
 
     line = {"metric": METRIC, "higher_is_better": True, "n_gpus": 1, "scaling": "weak",
             "vs_baseline": None, "dtype": "f32", "data": "synthetic",

@@ -64,7 +64,11 @@ typedef enum {
 
 typedef struct tau1_ctx tau1_ctx; /* opaque, owned by the library */
 
-typedef enum { TAU1_D3Q15 = 15, TAU1_D3Q19 = 19, TAU1_D3Q27 = 27 } tau1_lattice;
+/* D2Q9 is the two-dimensional lattice of the paper's validation runs
+ * (pressure-driven Poiseuille flow, lid-driven cavity): samples have nz = 1,
+ * F64 or F32 only, one thread per node; its node types and boundaries are
+ * described at tau1_desc. */
+typedef enum { TAU1_D2Q9 = 9, TAU1_D3Q15 = 15, TAU1_D3Q19 = 19, TAU1_D3Q27 = 27 } tau1_lattice;
 
 /* Arithmetic and storage of (rho - 1, u):
  *   TAU1_F64       FP64 compute, FP64 storage (parity mode);
@@ -113,12 +117,22 @@ typedef struct {
                                otherwise), 0 = dense, 1 = packed
                                (TAU1_E_UNSUPPORTED if no sample can be
                                packed: F64, kernel 0, other nx)            */
+    /* D2Q9 only (TAU1_E_UNSUPPORTED on the 3-D lattices when set).  Solid
+     * bytes there are node types: 0 fluid, 1 wall (halfway bounce-back),
+     * 2 moving wall (bounce-back plus the wall momentum 6 w_k rho (c_k . u_w)).
+     * g[2] must be 0; the z component of u0 is ignored.                   */
+    int32_t x_boundary;     /* 0 = periodic in x; 1 = constant-pressure
+                               (Zou-He) columns: fluid nodes at x = 0 hold
+                               rho_in, at x = nx - 1 rho_out (nx >= 3)      */
+    double rho_in, rho_out; /* > 0, used when x_boundary = 1              */
+    double wall_u[3];       /* velocity of the moving walls (z ignored)    */
 } tau1_desc;
 
 /* Static facts about a created context (host copy). */
 typedef struct {
     int32_t lattice, precision, n_samples;
-    int32_t kernel;          /* step kernel in use                          */
+    int32_t kernel;          /* step kernel in use: 0 per-node gather,
+                                1 z-march tiles, 2 D2Q9                      */
     int32_t tile;            /* tile shape index in use (z-march)           */
     int32_t graph_chunk;
     int32_t layout;          /* 1 if any sample is stored packed, else 0    */

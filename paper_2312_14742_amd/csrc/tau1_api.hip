@@ -50,7 +50,7 @@ struct Plan {
     std::vector<SampleHost> s;
 };
 
-bool valid_lattice(int q) { return q == 15 || q == 19 || q == 27; }
+bool valid_lattice(int q) { return q == 9 || q == 15 || q == 19 || q == 27; }
 bool valid_precision(int p) { return p >= kF64 && p <= kBF16; }
 
 tau1_status validate(const tau1_desc* d) {
@@ -61,6 +61,14 @@ tau1_status validate(const tau1_desc* d) {
     if (d->kernel < -1 || d->kernel > 1) return TAU1_E_INVALID;
     if (d->tile < -1 || d->tile >= kNumTiles) return TAU1_E_INVALID;
     if (d->layout < -1 || d->layout > 1) return TAU1_E_INVALID;
+    if (d->x_boundary < 0 || d->x_boundary > 1) return TAU1_E_INVALID;
+    for (int a = 0; a < 3; ++a)
+        if (!std::isfinite(d->wall_u[a])) return TAU1_E_INVALID;
+    if (d->x_boundary == 1 &&
+        !(std::isfinite(d->rho_in) && std::isfinite(d->rho_out) && d->rho_in > 0 &&
+          d->rho_out > 0))
+        return TAU1_E_INVALID;
+    if (d->lattice == 9 && d->g[2] != 0.0) return TAU1_E_INVALID;
     for (int a = 0; a < 3; ++a)
         if (!std::isfinite(d->g[a])) return TAU1_E_INVALID;
     if (d->f16_log2_scale_rho < 0 || d->f16_log2_scale_rho > 40 ||
@@ -72,7 +80,19 @@ tau1_status validate(const tau1_desc* d) {
         if (s.nx > (1 << 20) || s.ny > (1 << 20) || s.nz > (1 << 20)) return TAU1_E_INVALID;
         if (s.nx * s.ny > (int64_t(1) << 31)) return TAU1_E_INVALID;
         if (s.nx * s.ny * s.nz > (int64_t(1) << 36)) return TAU1_E_INVALID;
+        if (d->lattice == 9 && s.nz != 1) return TAU1_E_INVALID;
+        if (d->x_boundary == 1 && s.nx < 3) return TAU1_E_INVALID;
     }
+    return TAU1_OK;
+}
+
+// Valid requests this build does not serve: the D2Q9 validation lattice has
+// one kernel, in FP64 and FP32; its boundaries exist only there.
+tau1_status unsupported(const tau1_desc* d) {
+    if (d->lattice == 9 && (d->precision > kF32 || d->kernel != -1)) return TAU1_E_UNSUPPORTED;
+    if (d->lattice != 9 && (d->x_boundary != 0 || d->wall_u[0] != 0.0 || d->wall_u[1] != 0.0 ||
+                            d->wall_u[2] != 0.0))
+        return TAU1_E_UNSUPPORTED;
     return TAU1_OK;
 }
 
@@ -131,6 +151,7 @@ Plan make_plan(const tau1_desc* d, bool tables) {
         sd.block0 = blocks;
         blocks += (sd.n + kGatherBlock - 1) / kGatherBlock;
         zmarch_tiling(sd);
+        if (d->lattice == 9) sd.variant = -1;  // the D2Q9 kernel only
         maxn = std::max<int64_t>(maxn, sd.n);
     }
     // packed layout: by default for FP32 (there the step is bound by memory
@@ -189,6 +210,10 @@ Plan make_plan(const tau1_desc* d, bool tables) {
         if (sd.pk) {
             sd.chunk_tab = (int64_t)off;
             off = align_up(off + 16 * (size_t)sd.ny * sd.nz * kVariants[sd.variant].c, kAlign);
+        }
+        if (d->lattice == 9) {
+            sd.types = (int64_t)off;
+            off = align_up(off + (size_t)sd.n, kAlign);
         }
         for (int b = 0; b < 2; ++b) {
             sd.state[b] = (int64_t)off;
@@ -285,8 +310,16 @@ bool zmarch_eligible(const tau1_ctx* ctx) {
                             (int)ctx->plan.s.size());
 }
 
-// Launch geometry of one step kernel: z-march group g (kernel 1) or the
-// per-node gather over every sample (kernel 0).
+void* pick_d2q9(int p) {
+    switch (p) {
+        case kF64: return reinterpret_cast<void*>(&k_d2q9<kF64>);
+        case kF32: return reinterpret_cast<void*>(&k_d2q9<kF32>);
+    }
+    return nullptr;
+}
+
+// Launch geometry of one step kernel: z-march group g (kernel 1), the
+// per-node gather over every sample (kernel 0) or the D2Q9 kernel (2).
 Launch step_launch(const tau1_ctx* ctx, int kernel, int tile, int g) {
     Launch l{};
     if (kernel == 1) {
@@ -298,7 +331,7 @@ Launch step_launch(const tau1_ctx* ctx, int kernel, int tile, int g) {
         l.grid = dim3((unsigned)zmarch_grid(grp.args[0].ntiles, tile));
         l.shmem = 0;
     } else {
-        l.fn = pick_gather(ctx->lattice, ctx->precision);
+        l.fn = kernel == 2 ? pick_d2q9(ctx->precision) : pick_gather(ctx->lattice, ctx->precision);
         l.block = dim3(kGatherBlock);
         l.grid = dim3((unsigned)ctx->plan.total_blocks);
         l.shmem = 0;
@@ -451,6 +484,11 @@ tau1_status upload_sample_t(tau1_ctx* ctx, int s, const tau1_sample& in) {
         const tau1_status st = build_wall_list(ctx, sd);
         if (st != TAU1_OK) return st;
     }
+    if (sd.types) {
+        HIP_TRY(hipMemcpyAsync(ctx->base + sd.types, in.solid, (size_t)n, hipMemcpyHostToDevice,
+                               ctx->stream));
+        HIP_TRY(hipStreamSynchronize(ctx->stream));
+    }
     if (sd.pk) {
         const auto& tab = ctx->plan.s[s].ctab;
         HIP_TRY(hipMemcpyAsync(ctx->base + sd.chunk_tab, tab.data(), sizeof(uint32_t) * tab.size(),
@@ -468,11 +506,16 @@ tau1_status upload_sample_t(tau1_ctx* ctx, int s, const tau1_sample& in) {
         if (in.drho0)
             HIP_TRY(hipMemcpyAsync(st_d, in.drho0 + i0, sizeof(double) * len,
                                    hipMemcpyHostToDevice, ctx->stream));
-        if (in.u0)
-            for (int a = 0; a < 3; ++a)
+        if (in.u0) {
+            // D2Q9: two velocity components; the third is held at zero
+            const int ncomp = ctx->lattice == 9 ? 2 : 3;
+            for (int a = 0; a < ncomp; ++a)
                 HIP_TRY(hipMemcpyAsync(st_u + a * len, in.u0 + (int64_t)a * n + i0,
                                        sizeof(double) * len, hipMemcpyHostToDevice,
                                        ctx->stream));
+            if (ncomp == 2)
+                HIP_TRY(hipMemsetAsync(st_u + 2 * len, 0, sizeof(double) * len, ctx->stream));
+        }
         hipLaunchKernelGGL(k_upload<P>, dim3((unsigned)((len + 255) / 256)), dim3(256), 0,
                            ctx->stream, ctx->args[0], s, st_solid, in.drho0 ? st_d : nullptr,
                            in.u0 ? st_u : nullptr, i0, len);
@@ -610,7 +653,8 @@ const char* tau1_strerror(tau1_status s) {
 
 tau1_status tau1_workspace_size(const tau1_desc* desc, size_t* bytes) {
     if (!bytes) return TAU1_E_INVALID;
-    const tau1_status v = validate(desc);
+    tau1_status v = validate(desc);
+    if (v == TAU1_OK) v = unsupported(desc);
     if (v != TAU1_OK) return v;
     try {
         const Plan p = make_plan(desc, false);
@@ -626,6 +670,7 @@ tau1_status tau1_create(const tau1_desc* desc, tau1_ctx** out) {
     if (!out) return TAU1_E_INVALID;
     *out = nullptr;
     tau1_status v = validate(desc);
+    if (v == TAU1_OK) v = unsupported(desc);
     if (v != TAU1_OK) return v;
     // non-finite initial fields are rejected before any GPU work
     for (int i = 0; i < desc->n_samples; ++i) {
@@ -692,6 +737,11 @@ tau1_status tau1_create(const tau1_desc* desc, tau1_ctx** out) {
         a.inv_scale_rho = std::ldexp(1.0f, -lsr);
         a.scale_u = std::ldexp(1.0f, lsu);
         a.inv_scale_u = std::ldexp(1.0f, -lsu);
+        a.xbc = desc->x_boundary;
+        a.din = desc->x_boundary ? desc->rho_in - 1.0 : 0.0;
+        a.dout = desc->x_boundary ? desc->rho_out - 1.0 : 0.0;
+        a.uw[0] = desc->wall_u[0];
+        a.uw[1] = desc->wall_u[1];
     }
     // fluid counts, and for z-march samples the rows holding a fluid node
     // (host marshalling of the geometry)
@@ -741,7 +791,7 @@ tau1_status tau1_create(const tau1_desc* desc, tau1_ctx** out) {
         delete ctx;
         return TAU1_E_UNSUPPORTED;
     }
-    ctx->kernel = desc->kernel >= 0 ? desc->kernel : (zm ? 1 : 0);
+    ctx->kernel = ctx->lattice == 9 ? 2 : desc->kernel >= 0 ? desc->kernel : (zm ? 1 : 0);
     const bool packed = ctx->plan.packed;
     int tile = desc->tile >= 0 ? desc->tile : zmarch_default_tile(packed);
     if (ctx->kernel == 1 && desc->tile < 0 && !ctx->cache.empty()) {
@@ -886,7 +936,8 @@ tau1_status tau1_get_info(const tau1_ctx* ctx, tau1_info* info) {
     info->n_fluid = ctx->n_fluid;
     info->steps_done = ctx->steps_done;
     const double s = storage_bytes(ctx->precision);
-    info->bytes_per_step = 2.0 * 4.0 * s * (double)ctx->n_fluid + (double)ctx->n_nodes / 8.0;
+    const double vals = ctx->lattice == 9 ? 3.0 : 4.0;  // d + 1 stored values per node
+    info->bytes_per_step = 2.0 * vals * s * (double)ctx->n_fluid + (double)ctx->n_nodes / 8.0;
     int64_t items = 0;
     if (ctx->kernel == 1)
         for (const auto& g : ctx->zgroups) items += g.args[0].ntiles;

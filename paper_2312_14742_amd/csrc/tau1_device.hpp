@@ -62,6 +62,18 @@ template <> struct Lattice<27> {
                             w_edge = 1.0 / 54.0, w_corner = 1.0 / 216.0;
 };
 
+// D2Q9, the two-dimensional lattice of the paper's validation runs (z = 0):
+// rest, faces, then the diagonals as opposite pairs, as above.
+template <> struct Lattice<9> {
+    static constexpr int q = 9;
+    static constexpr Dir c[9] = {
+        {0, 0, 0},
+        {1, 0, 0}, {-1, 0, 0}, {0, 1, 0}, {0, -1, 0},
+        {1, 1, 0}, {-1, -1, 0}, {1, -1, 0}, {-1, 1, 0}};
+    static constexpr double w_rest = 4.0 / 9.0, w_face = 1.0 / 9.0,
+                            w_edge = 1.0 / 36.0, w_corner = 0.0;
+};
+
 // Weight of a direction from its number of nonzero components.
 template <int Q>
 __host__ __device__ constexpr double weight(int k) {
@@ -148,6 +160,8 @@ struct SampleDev {
     int64_t wall_off;     // byte offset of the wall-list row offsets (uint32, rows + 1)
     int64_t wall_list;    // byte offset of the wall-list entries (one per wall node)
     int64_t chunk_tab;    // byte offset of the chunk table (packed layout)
+    int64_t types;        // D2Q9: byte offset of the node types (uint8: 0 fluid,
+                          // 1 wall, 2 moving wall); 0 otherwise
     int32_t nx, ny, nz;
     int32_t words;        // mask words per (y, z) row: ceil(nx / 32)
     int32_t xwords;       // extended-mask words per row

@@ -19,6 +19,12 @@ struct StepArgs {
     double gh[3];               // g / 2 (FP64)
     float ghf[3];               // g / 2 (FP32)
     float scale_rho, inv_scale_rho, scale_u, inv_scale_u;  // F16 storage
+    // D2Q9 boundaries: Zou-He pressure columns at x = 0 and nx - 1 (xbc = 1)
+    // with densities 1 + din, 1 + dout; velocity of the moving walls
+    int32_t xbc;
+    int32_t pad2;
+    double din, dout;
+    double uw[2];
 };
 
 template <int P>
@@ -128,6 +134,113 @@ __global__ __launch_bounds__(kGatherBlock) void k_gather(StepArgs a) {
     St::store(post + st, i, ux + ghx, su);
     St::store(post + 2 * st, i, uy + ghy, su);
     St::store(post + 3 * st, i, uz + ghz, su);
+}
+
+// ---------------------------------------------------------------------------
+// D2Q9 step of the validation workloads (nz = 1), one thread per node, pull
+// form as k_gather, with node types: a wall source (type 1) returns the node's
+// own equilibrium in the opposite direction (halfway bounce-back, Eq. (11));
+// a moving wall (type 2) adds the wall's momentum to it,
+//   f_k(x) = f_opp(k)(x) + 6 w_k rho(x) (c_k . u_wall).
+// With a.xbc the fluid nodes of columns x = 0 and nx - 1 are constant-pressure
+// nodes (Zou-He): the populations that would come from outside are unknown,
+// the known ones fix rho u_x through
+//   inlet:  rho_in u_x  = drho_in  - [f0 + f3 + f4 + 2 (f2 + f6 + f8)]
+//   outlet: rho_out u_x = [f0 + f3 + f4 + 2 (f1 + f5 + f7)] - drho_out
+// (values minus their weights), and the node's new state is (rho_b, u_x, 0).
+// FP64 reproduces the oracle's roundings (contraction off).
+// ---------------------------------------------------------------------------
+template <int P>
+__global__ __launch_bounds__(kGatherBlock) void k_d2q9(StepArgs a) {
+#pragma clang fp contract(off)
+    using St = Storage<P>;
+    using S = typename St::S;
+    using T = typename St::T;
+    using L = Lattice<9>;
+    const int s = sample_of_block(a.samples, a.nsamples, blockIdx.x);
+    const SampleDev& sd = a.samples[s];
+    const int64_t i = (int64_t)(blockIdx.x - sd.block0) * kGatherBlock + threadIdx.x;
+    if (i >= sd.n) return;
+    const int nx = sd.nx, ny = sd.ny;
+    const int x = (int)(i % nx);
+    const int y = (int)(i / nx);
+    const uint8_t* type = a.base + sd.types;
+    if (type[i]) return;
+
+    const S* pre = reinterpret_cast<const S*>(a.base + sd.state[a.parity]);
+    S* post = reinterpret_cast<S*>(a.base + sd.state[a.parity ^ 1]);
+    const int64_t st = sd.stride;
+    const T d0 = St::load(pre, i, (T)1);
+    const T v0x = St::load(pre + st, i, (T)1);
+    const T v0y = St::load(pre + 2 * st, i, (T)1);
+    const T uwx = (T)a.uw[0], uwy = (T)a.uw[1];
+    const bool pressure = a.xbc && (x == 0 || x == nx - 1);
+
+    T f[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+        const int cx = L::c[k].x, cy = L::c[k].y;
+        int sx = x - cx, sy = y - cy;
+        sy += sy < 0 ? ny : 0; sy -= sy >= ny ? ny : 0;
+        if (a.xbc && (sx < 0 || sx >= nx)) {
+            f[k] = 0;  // unknown of a pressure column; not used
+            continue;
+        }
+        sx += sx < 0 ? nx : 0; sx -= sx >= nx ? nx : 0;
+        const int64_t j = sx + (int64_t)nx * sy;
+        const int tj = type[j];
+        T ds, vx, vy, ex, ey;
+        if (tj == 0) {
+            ds = St::load(pre, j, (T)1);
+            vx = St::load(pre + st, j, (T)1);
+            vy = St::load(pre + 2 * st, j, (T)1);
+            ex = (T)cx; ey = (T)cy;
+        } else {
+            ds = d0; vx = v0x; vy = v0y;
+            ex = (T)-cx; ey = (T)-cy;
+        }
+        const T rho = (T)1 + ds;
+        const T cu = ex * vx + ey * vy;
+        const T vv = vx * vx + vy * vy;
+        const T p = ((T)3 * cu + ((T)4.5 * cu) * cu) - (T)1.5 * vv;
+        T fk = (T)weight<9>(k) * (ds + rho * p);
+        if (tj == 2) {
+            const T cw = (T)cx * uwx + (T)cy * uwy;
+            fk += (T)6 * (T)weight<9>(k) * ((T)1 + d0) * cw;
+        }
+        f[k] = fk;
+    }
+    const T ghx = gh_of<T>(a, 0), ghy = gh_of<T>(a, 1);
+    T d, ux, uy;
+    if (pressure) {
+        const bool inlet = x == 0;
+        const T db = (T)(inlet ? a.din : a.dout);
+        if (inlet) {
+            const T sk = (f[0] + f[3] + f[4]) + (T)2 * ((f[2] + f[6]) + f[8]);
+            ux = (db - sk) / ((T)1 + db) + ghx;
+        } else {
+            const T sk = (f[0] + f[3] + f[4]) + (T)2 * ((f[1] + f[5]) + f[7]);
+            ux = (sk - db) / ((T)1 + db) + ghx;
+        }
+        d = db;
+        uy = ghy;
+    } else {
+        T jx = 0, jy = 0;
+        d = 0;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+            d += f[k];
+            jx += (T)L::c[k].x * f[k];
+            jy += (T)L::c[k].y * f[k];
+        }
+        const T r = (T)1 / ((T)1 + d);
+        ux = jx * r + ghx;
+        uy = jy * r + ghy;
+    }
+    St::store(post, i, d, (T)1);
+    St::store(post + st, i, ux + ghx, (T)1);
+    St::store(post + 2 * st, i, uy + ghy, (T)1);
+    St::store(post + 3 * st, i, (T)0, (T)1);
 }
 
 // State upload: staging FP64 (drho0, u0) for nodes [i0, i0 + len) of one

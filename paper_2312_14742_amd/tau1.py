@@ -57,7 +57,10 @@ class tau1_desc(ctypes.Structure):
                 ("f16_log2_scale_rho", ctypes.c_int32),
                 ("f16_log2_scale_u", ctypes.c_int32),
                 ("tune_cache", ctypes.c_char_p),
-                ("layout", ctypes.c_int32)]
+                ("layout", ctypes.c_int32),
+                ("x_boundary", ctypes.c_int32),
+                ("rho_in", ctypes.c_double), ("rho_out", ctypes.c_double),
+                ("wall_u", ctypes.c_double * 3)]
 
 
 class tau1_info(ctypes.Structure):
@@ -150,7 +153,7 @@ class Sample:
 
 
 def _desc(samples, lattice, precision, g, graph_chunk, kernel, tile, f16_scales,
-          tune_cache, layout=-1):
+          tune_cache, layout=-1, x_boundary=0, rho_in=1.0, rho_out=1.0, wall_u=(0.0, 0.0, 0.0)):
     arr = (tau1_sample * len(samples))(*[s.c_struct() for s in samples])
     d = tau1_desc()
     d.lattice = int(lattice)
@@ -166,15 +169,21 @@ def _desc(samples, lattice, precision, g, graph_chunk, kernel, tile, f16_scales,
     d.f16_log2_scale_u = int(f16_scales[1])
     d.tune_cache = None if tune_cache is None else os.fsencode(tune_cache)
     d.layout = int(layout)
+    d.x_boundary = int(x_boundary)
+    d.rho_in = float(rho_in)
+    d.rho_out = float(rho_out)
+    for a in range(3):
+        d.wall_u[a] = float(wall_u[a]) if a < len(wall_u) else 0.0
     return d, arr
 
 
 def workspace_size(samples, lattice=19, precision="f32", g=(0.0, 0.0, 0.0),
-                   graph_chunk=0, kernel=-1, tile=-1, f16_scales=(0, 0), layout=-1) -> int:
+                   graph_chunk=0, kernel=-1, tile=-1, f16_scales=(0, 0), layout=-1,
+                   x_boundary=0, rho_in=1.0, rho_out=1.0, wall_u=(0.0, 0.0, 0.0)) -> int:
     """Device bytes tau1_create needs (host-only call)."""
     samples = [s if isinstance(s, Sample) else Sample(*s) for s in samples]
     d, keep = _desc(samples, lattice, precision, g, graph_chunk, kernel, tile,
-                    f16_scales, None, layout)
+                    f16_scales, None, layout, x_boundary, rho_in, rho_out, wall_u)
     n = ctypes.c_size_t(0)
     _check(_lib().tau1_workspace_size(ctypes.byref(d), ctypes.byref(n)),
            "tau1_workspace_size")
@@ -188,12 +197,16 @@ class Sim:
     ``precision`` is one of "f64", "f32", "f16", "bf16".  ``kernel`` -1 picks
     automatically, 0 forces the per-node gather kernel, 1 the z-march tiles.
     ``layout`` -1 picks the state layout automatically, 0 is dense, 1 packed
-    (all-solid lane chunks not stored).
+    (all-solid lane chunks not stored).  ``lattice=9`` is the D2Q9 validation
+    lattice (samples of shape (1, ny, nx); solid values 0 fluid, 1 wall,
+    2 moving wall with velocity ``wall_u``; ``x_boundary=1`` puts Zou-He
+    pressure columns at x = 0 (``rho_in``) and x = nx - 1 (``rho_out``)).
     """
 
     def __init__(self, samples, lattice=19, precision="f32", g=(0.0, 0.0, 0.0),
                  graph_chunk=0, kernel=-1, tile=-1, f16_scales=(0, 0),
-                 tune_cache=None, device="cuda:0", layout=-1):
+                 tune_cache=None, device="cuda:0", layout=-1, x_boundary=0, rho_in=1.0,
+                 rho_out=1.0, wall_u=(0.0, 0.0, 0.0)):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("Tau1 Sim needs a ROCm GPU (torch.cuda is unavailable)")
@@ -205,7 +218,7 @@ class Sim:
         self.g = tuple(float(x) for x in g)
         lib = _lib()
         d, keep = _desc(self.samples, lattice, precision, g, graph_chunk, kernel, tile,
-                        f16_scales, tune_cache, layout)
+                        f16_scales, tune_cache, layout, x_boundary, rho_in, rho_out, wall_u)
         n = ctypes.c_size_t(0)
         _check(lib.tau1_workspace_size(ctypes.byref(d), ctypes.byref(n)),
                "tau1_workspace_size")
