@@ -228,21 +228,47 @@ def reduce(st: State, axis: int, g_axis: float):
 # Two-dimensional validation lattice (D2Q9)
 # ---------------------------------------------------------------------------
 _lib2d = None
+_override2d = None
+
+
+def _open2d(path: str):
+    lib = ctypes.CDLL(path)
+    P, L, I, D = ctypes.c_void_p, ctypes.c_long, ctypes.c_int, ctypes.c_double
+    lib.tau1o2_lattice.argtypes = [P, P, P]
+    lib.tau1o2_run.argtypes = [L, L, P, P, P, P, P, P, I, D, D, L, I]
+    lib.tau1o2_bgk_run.argtypes = [L, L, P, P, P, P, P, P, I, D, D, D, L]
+    lib.tau1o2_reduce.argtypes = [L, L, P, P, P, P, P]
+    return lib
 
 
 def _load2d():
     global _lib2d
+    if _override2d is not None:
+        return _override2d
     if _lib2d is None:
         if not os.path.exists(_LIB2D):
             build(force=True)
-        lib = ctypes.CDLL(_LIB2D)
-        P, L, I, D = ctypes.c_void_p, ctypes.c_long, ctypes.c_int, ctypes.c_double
-        lib.tau1o2_lattice.argtypes = [P, P, P]
-        lib.tau1o2_run.argtypes = [L, L, P, P, P, P, P, P, I, D, D, L, I]
-        lib.tau1o2_bgk_run.argtypes = [L, L, P, P, P, P, P, P, I, D, D, D, L]
-        lib.tau1o2_reduce.argtypes = [L, L, P, P, P, P, P]
-        _lib2d = lib
+        _lib2d = _open2d(_LIB2D)
     return _lib2d
+
+
+class use_library_2d:
+    """Context manager: route the 2-D calls to another build of the 2-D
+    oracle (the mutation tests' deliberately broken copies)."""
+
+    def __init__(self, path: str):
+        self._lib = _open2d(path)
+
+    def __enter__(self):
+        global _override2d
+        self._prev = _override2d
+        _override2d = self._lib
+        return self
+
+    def __exit__(self, *exc):
+        global _override2d
+        _override2d = self._prev
+        return False
 
 
 def lattice_2d():
