@@ -150,3 +150,26 @@ def test_lid_driven_cavity_on_gpu():
     assert np.abs(ub[1] - ua[1][:, ::-1]).max() <= 1e-5 * scale
     a.close()
     b.close()
+
+
+def test_d2q9_batch_equals_solo_bitwise():
+    """Several 2-D samples of different sizes in one context (one launch per
+    step for all) give each sample's solo bits, with pressure columns."""
+    states = [random_state(40, 12, seed=21, pressure=True, wall_frac=0.05),
+              random_state(17, 9, seed=22, pressure=True, wall_frac=0.1),
+              random_state(64, 30, seed=23, pressure=True, wall_frac=0.0)]
+    bc = dict(x_boundary=1, rho_in=1.004, rho_out=0.998)
+    samples = []
+    for st in states:
+        ny, nx = st.types.shape
+        u3 = np.zeros((3, 1, ny, nx))
+        u3[:2, 0] = st.u
+        samples.append(tau1.Sample(st.types[None], st.drho[None], u3))
+    sim = tau1.Sim(samples, lattice=9, precision="f32", graph_chunk=50, **bc)
+    sim.step(120)
+    for i, st in enumerate(states):
+        d, u = sim.moments(i)
+        solo, ds, us = gpu_run(st, 120, prec="f32", graph_chunk=50, **dict(bc))
+        assert d[0].tobytes() == ds.tobytes() and u[:2, 0].tobytes() == us.tobytes(), i
+        solo.close()
+    sim.close()
