@@ -793,6 +793,7 @@ __device__ __forceinline__ void zr_step(const ZrItem<P, G, C, K>& it, int zs, Pl
 
     float* own = nullptr;
     float* spare = nullptr;
+    int vn[C];  // packed layout: the lane's chunk offsets in the next plane's own row
     if constexpr (SHARE) {
         // slots of this plane (parity of zs) and of the next one
         const int b = zs & 1;
@@ -838,6 +839,22 @@ __device__ __forceinline__ void zr_step(const ZrItem<P, G, C, K>& it, int zs, Pl
     // next plane's own row once this one's registers are free
     if constexpr (ROLL) load_row(it, rp_, rp);
     else if constexpr (!SHARE) load_row(it, rm_, rm);
+    // shared rows: the next plane's own row, requested as soon as this
+    // plane's own row has been pushed (its registers are free then; any
+    // earlier and they would not fit two waves per SIMD), so its loads land
+    // during the rest of the step.  Only where the workgroup's LDS already
+    // holds the CU at two waves per SIMD (six or more nodes per lane): for
+    // shorter rows the extra live registers would cost occupancy.  D3Q27's
+    // larger sums keep the request at the end of the step.
+    constexpr bool EARLY = Q < 27 && PX >= 6;
+    if constexpr (EARLY) {
+        if constexpr (PK) {
+            chunk_voffs(it, tn_own, vn);
+            load_row_pk(it, vn, ahead);
+        } else if constexpr (SHARE) {
+            load_row(it, wrapi((zs + 1) % nz, nz) * ny + it.yc, ahead);
+        }
+    }
     // ---- neighbour rows: y-1 sends its c_y = +1 directions, y+1 its c_y = -1
     {
         Src s[PX];
@@ -908,12 +925,15 @@ __device__ __forceinline__ void zr_step(const ZrItem<P, G, C, K>& it, int zs, Pl
         }
     }
     fluid_prev = fown;
-    // shared rows: the next plane's own row, requested once this plane's
-    // registers are free (it lands while the next step starts)
+    if constexpr (!EARLY) {
+        if constexpr (PK) {
+            chunk_voffs(it, tn_own, vn);
+            load_row_pk(it, vn, ahead);
+        } else if constexpr (SHARE) {
+            load_row(it, wrapi((zs + 1) % nz, nz) * ny + it.yc, ahead);
+        }
+    }
     if constexpr (PK) {
-        int vn[C];
-        chunk_voffs(it, tn_own, vn);
-        load_row_pk(it, vn, ahead);
 #pragma unroll
         for (int c = 0; c < C; ++c) {
             pk.vst[c] = pk.vcur[c];
@@ -921,8 +941,6 @@ __device__ __forceinline__ void zr_step(const ZrItem<P, G, C, K>& it, int zs, Pl
         }
         if (!it.share_m) chunk_voffs(it, tn_m, pk.vm);
         if (!it.share_p) chunk_voffs(it, tn_p, pk.vp);
-    } else if constexpr (SHARE) {
-        load_row(it, wrapi((zs + 1) % nz, nz) * ny + it.yc, ahead);
     }
 }
 
