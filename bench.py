@@ -11,7 +11,9 @@ fluid node plus one mask bit per node (complexity table of the paper).
 Sections (``--sections``, default all):
   main       D3Q19, 512^3 sphere packing (r = 12, porosity 0.7, seed 3000),
              FP32, g = 1e-6 along x; timed for exactly ``--steps`` steps.  This
-             is the headline value and carries the roofline object.
+             is the headline value and carries the roofline object; the same
+             region is then timed ``--repeats`` - 1 more times for the median
+             and the spread (``repeats``).
   lattices   D3Q15 and D3Q27 on the same geometry (500 steps each).
   precision  D3Q19 512^3 porosity 0.6 (r = 12, seed 4000) with (rho - 1, u)
              stored in FP32, FP16 (scaled) and BF16, 2000 steps each; error of
@@ -47,6 +49,7 @@ import argparse
 import hashlib
 import json
 import os
+import statistics
 import sys
 import time
 
@@ -72,6 +75,9 @@ def parse_args(argv=None):
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=500, help="timed steps of the main workload")
     ap.add_argument("--warmup", type=int, default=100, help="untimed steps before timing")
+    ap.add_argument("--repeats", type=int, default=5,
+                    help="timed regions of --steps steps for the main workload; the first "
+                         "gives the headline value, all of them the median and spread")
     ap.add_argument("--sections", default="main,lattices,precision,batch,porosity,validation")
     ap.add_argument("--tile", type=int, default=-1, help="z-march tile; -1 = autotune")
     ap.add_argument("--graph-chunk", type=int, default=100)
@@ -199,10 +205,11 @@ class GpuRunner:
         return wall, ev
 
     def case(self, samples, lattice, precision, steps, warmup, graph_chunk, tile,
-             g=G_MAIN, label="", layout=-1):
+             g=G_MAIN, label="", layout=-1, repeats=1):
         sim = self.make(samples, lattice, precision, g, graph_chunk, tile, layout=layout)
         wall, ev = self.time_steps(sim, steps, warmup)
         inf = sim.info()
+        walls = [wall] + [self.time_steps(sim, steps, 0)[0] for _ in range(repeats - 1)]
         res = {
             "gflups": inf["n_fluid"] * steps / wall / 1e9,
             "ms_per_step": wall / steps * 1e3,
@@ -214,6 +221,13 @@ class GpuRunner:
             "bytes_per_step": inf["bytes_per_step"],
         }
         res["frac"] = res["alg_gbs"] / PEAK_HBM_GBS
+        if repeats > 1:
+            rates = sorted(inf["n_fluid"] * steps / w / 1e9 for w in walls)
+            res["repeats"] = {"n": repeats, "steps_each": steps,
+                              "median_gflups": statistics.median(rates),
+                              "min_gflups": rates[0], "max_gflups": rates[-1]}
+            log(f"{label}: {repeats} timed regions, median {res['repeats']['median_gflups']:.2f} "
+                f"GFLUPS (min {rates[0]:.2f}, max {rates[-1]:.2f})")
         log(f"{label}: {res['gflups']:.2f} GFLUPS, {res['alg_gbs']:.0f} GB/s algorithmic "
             f"({100 * res['frac']:.1f}% of 8 TB/s), tile {res['tile']}")
         return sim, res
@@ -473,7 +487,8 @@ def main(argv=None):
     main_res = None
     if "main" in sections:
         sim, main_res = gr.case([tau1.Sample(geos["main"].solid)], 19, "f32", args.steps,
-                                args.warmup, args.graph_chunk, args.tile, label="main D3Q19 f32")
+                                args.warmup, args.graph_chunk, args.tile, label="main D3Q19 f32",
+                                repeats=max(1, args.repeats))
         sim.close()
         copy_bytes = 2 * 16 * main_res["n_nodes"]
         main_res["copy_gbs"] = gr.copy_gbs(copy_bytes)
@@ -514,6 +529,7 @@ def main(argv=None):
         line.update({
             "value": main_res["gflups"], "unit": "GFLUPS",
             "ms_per_step": main_res["ms_per_step"],
+            "repeats": main_res.get("repeats"),
             "config": {"workload": "Tau1 D3Q19 FP32, 512^3 periodic sphere packing "
                                    "(r=12, target porosity 0.7, seed 3000), g=1e-6 along x",
                        "nx": 512, "ny": 512, "nz": 512, "porosity": geo.porosity,
