@@ -42,7 +42,7 @@ def build(force: bool = True) -> str:
     """Compile the oracle libraries with gcc; returns the 3-D library path."""
     for src, lib in ((_SRC, _LIB), (_SRC2D, _LIB2D)):
         if force or not os.path.exists(lib):
-            tmp = lib + ".tmp"
+            tmp = f"{lib}.{os.getpid()}.tmp"      # concurrent builders never share it
             subprocess.run(["gcc", *CFLAGS, src, "-o", tmp, "-lm"], check=True)
             os.replace(tmp, lib)
     return _LIB
