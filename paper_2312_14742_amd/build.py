@@ -56,7 +56,7 @@ def build(verbose: bool = False, extra: list[str] | None = None, jobs: int | Non
         logs = list(ex.map(_run, cmds))
     if verbose:
         sys.stderr.write("".join(logs))
-    tmp = f"{LIB}.{os.getpid()}.tmp"
+    tmp = LIB + ".tmp"
     _run([hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", *[o for _, o, _ in units],
           "-o", tmp])
     os.replace(tmp, LIB)
