@@ -15,7 +15,7 @@ import numpy as np
 _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libtau1.so")
 
-LATTICES = (15, 19, 27)
+LATTICES = (9, 15, 19, 27)       # D2Q9 (validation lattice) and the 3-D sets
 PRECISIONS = {"f64": 0, "f32": 1, "f16": 2, "bf16": 3}
 
 TAU1_OK = 0
