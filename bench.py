@@ -18,8 +18,8 @@ Sections (``--sections``, default all):
   precision  D3Q19 512^3 porosity 0.6 (r = 12, seed 4000) with (rho - 1, u)
              stored in FP32, FP16 (scaled) and BF16, 2000 steps each; error of
              each mode on the 128^3 crop after 2000 steps against the FP64 mode
-             of the library (and against the FP64 oracle with
-             ``--oracle-accuracy``, which takes minutes of CPU time).
+             of the library (the same crop against the FP64 oracle is a GPU
+             test).
   batch      64 uneven porous samples (sides 64..320, porosity U[0.4, 0.95],
              radius U[4, 16], seeds 5000+i) in one launch per step, 100-step
              graphs, autotuned tiles, 1000 steps; against the same samples run
@@ -86,8 +86,6 @@ def parse_args(argv=None):
     ap.add_argument("--batch-steps", type=int, default=1000)
     ap.add_argument("--porosity-steps", type=int, default=1000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--oracle-accuracy", action="store_true",
-                    help="also compare the 128^3 crop with the FP64 oracle (slow)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run the copy kernel (for counter calibration)")
     return ap.parse_args(argv)
@@ -274,22 +272,6 @@ def precision_section(gr, geo, args, out):
                "mass_drift": (m - m0) / m0}
         modes.setdefault(prec, {})["crop128_2000_steps"] = acc
         log(f"crop accuracy {prec}: {acc}")
-    if args.oracle_accuracy:
-        import oracle
-        t = time.perf_counter()
-        st = oracle.run(19, oracle.State(crop), G_MAIN, steps)
-        m_o, k_o = oracle.reduce(st, 0, G_MAIN[0])
-        log(f"oracle crop run {time.perf_counter() - t:.0f} s")
-        for prec in ("f64", "f32", "f16", "bf16"):
-            sim = gr.make([tau1.Sample(crop)], 19, prec, G_MAIN, args.graph_chunk, -1)
-            sim.step(steps)
-            _, u = sim.moments(0, allow_nonfinite=True)
-            k, m = sim.permeability(0, 0)
-            sim.close()
-            modes[prec]["crop128_2000_steps"].update({
-                "u_rel_l2_vs_oracle": rel_l2(u, st.u, fluid),
-                "k_rel_err_vs_oracle": abs(k - k_o) / abs(k_o),
-                "mass_drift_oracle": (m_o - m0) / m0})
     out["precision_modes"] = {
         "workload": "D3Q19 512^3 sphere packing r=12 porosity 0.6 seed 4000, g=1e-6 x, "
                     f"{args.precision_steps} steps per mode; accuracy on the 128^3 crop "
