@@ -9,13 +9,20 @@ The oracle cannot run 1000 steps of 256^3, so each porosity checks:
   of the oracle on the small cases) on the same input, within
   1000 steps x 2 x 2^-24 relative, FP32 rounding growing at most linearly;
 - mass conservation: sum of rho over the fluid nodes stays N_f to 1e-9;
-and across the sweep the permeability must grow with the porosity."""
+and across the sweep the permeability must grow with the porosity.
+
+At porosity 0.7 the whole 1000-step run is also compared with the oracle's
+1000 steps (about 1.2e10 node updates of the FP64 oracle): FP64 mode to the
+FP64 parity bar, FP32 rel-L2(u) and permeability within 1000 x 2 x 2^-24."""
+import time
+
 import numpy as np
 import pytest
 
+import oracle
 from paper_2312_14742_amd import inputs, tau1
 
-from gpu_helpers import check_step, sample_nodes
+from gpu_helpers import TOL_F64, check_step, rel_l2, sample_nodes
 
 pytestmark = pytest.mark.gpu
 
@@ -56,3 +63,32 @@ def test_permeability_grows_with_porosity():
         pytest.skip("needs every porosity of the sweep")
     ks = [_K[p] for p in PHIS]
     assert all(a < b for a, b in zip(ks, ks[1:])), ks
+
+
+@pytest.mark.timeout(600)    # the oracle's 1000 steps take about 90 s on 16 host threads
+def test_porosity_07_full_run_against_oracle():
+    i, phi = 2, 0.7
+    geo = inputs.spheres(256, 256, 256, 8.0, phi, seed=2000 + i)
+    fl = geo.solid == 0
+    print(f"[case] 256^3 r=8 porosity {phi}: oracle {STEPS} steps", flush=True)
+    t = time.perf_counter()
+    ref = oracle.run(19, oracle.State(geo.solid), G, STEPS)
+    m_ref, k_ref = oracle.reduce(ref, 0, G[0])
+    print(f"[oracle] {time.perf_counter() - t:.1f} s", flush=True)
+    for prec in ("f64", "f32"):
+        with tau1.Sim([tau1.Sample(geo.solid)], lattice=19, precision=prec, g=G,
+                      graph_chunk=100) as sim:
+            sim.step(STEPS)
+            drho, u = sim.moments(0)
+            k, m = sim.permeability(0, 0)
+        e_u = rel_l2(u, ref.u, fl)
+        e_k = abs(k - k_ref) / abs(k_ref)
+        print(f"[err] full run {prec}: rel-L2(u) {e_u:.3e}, k rel {e_k:.3e}", flush=True)
+        if prec == "f64":
+            assert np.abs(drho - ref.drho).max() <= TOL_F64
+            assert np.abs(u - ref.u).max() <= TOL_F64 * np.abs(ref.u).max()
+            assert e_k <= 1e-12
+            assert abs(m - m_ref) <= 1e-12 * geo.n_fluid
+        else:
+            assert e_u <= STEPS * 2.0 * 2.0 ** -24
+            assert e_k <= STEPS * 2.0 * 2.0 ** -24
