@@ -52,6 +52,32 @@ def test_config1_channel_f64(kernel):
     sim.close()
 
 
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("q", LATTICES)
+def test_config1_channel_steady_state(q, prec):
+    """The 32^3 channel after 20000 steps against the mathematics, not the
+    oracle: the discrete steady profile of halfway bounce-back at tau = 1
+    (the Poiseuille parabola of the 30 fluid layers plus the uniform slip
+    g/4) and its Darcy permeability (N^3 + N) / (12 (N + 2)) = 70.390625 for
+    N = 30.  FP64 to 1e-11 relative (the oracle's own pin); FP32 within
+    20000 x 2 x 2^-24 (linear growth of FP32 rounding)."""
+    solid = _config1()
+    g = 1e-6
+    steps = 20000
+    print(f"[case] config1 steady q={q} {prec}", flush=True)
+    sim, out = run_gpu([(solid,)], q, prec, (g, 0.0, 0.0), steps, graph_chunk=100)
+    k, mass = sim.permeability(0, 0)
+    sim.close()
+    z = np.arange(1, 31, dtype=np.float64)
+    ref = g / (2.0 / 6.0) * (z - 0.5) * (30.5 - z) + g / 4.0
+    u = out[0][1]
+    tol = 1e-11 if prec == "f64" else steps * 2.0 * 2.0 ** -24
+    assert np.abs(u[0][1:-1] - ref[:, None, None]).max() <= tol * ref.max()
+    assert np.abs(u[1:]).max() <= tol * ref.max()
+    assert abs(k - 70.390625) <= tol * 70.390625
+    assert abs(mass - 30.0 * 32 * 32) <= (1e-12 if prec == "f64" else 1e-9) * mass
+
+
 SMALL = [(1, 1, 1), (2, 2, 2), (3, 3, 3), (5, 5, 5), (7, 7, 7), (5, 3, 7),
          (1, 4, 6), (33, 9, 4), (70, 37, 5)]
 
