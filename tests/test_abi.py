@@ -88,6 +88,31 @@ def test_invalid_dims_rejected(lib):
     assert lib.tau1_workspace_size(ctypes.byref(d), ctypes.byref(n)) == tau1.TAU1_E_INVALID
 
 
+@pytest.mark.parametrize("dims", [
+    (1, 1, (1 << 20) + 1),                 # nx above 2^20
+    (1, (1 << 20) + 1, 1),                 # ny above 2^20
+    ((1 << 20) + 1, 1, 1),                 # nz above 2^20
+    (1, (1 << 11) + 1, 1 << 20),           # nx * ny above 2^31
+    ((1 << 5) + 1, 1 << 15, 1 << 16),      # nx * ny * nz above 2^36
+])
+def test_dimension_limits_rejected(lib, dims):
+    """Rejected by validation before the solid array is read (a 4^3 array
+    stands in for the oversized one)."""
+    d, keep = _desc_for([(np.zeros((4, 4, 4), np.uint8),)])
+    keep[0].nz, keep[0].ny, keep[0].nx = dims
+    n = ctypes.c_size_t(0)
+    assert lib.tau1_workspace_size(ctypes.byref(d), ctypes.byref(n)) == tau1.TAU1_E_INVALID
+
+
+def test_longest_row_accepted(lib):
+    """A single row of 2^20 nodes is the largest extent accepted (served by
+    the per-node gather kernel: no z-march lane layout has rows that long)."""
+    solid = np.zeros((1, 1, 1 << 20), np.uint8)
+    solid[0, 0, ::7] = 1
+    n = tau1.workspace_size([(solid,)], precision="f32")
+    assert n >= 2 * 4 * 4 * (1 << 20)
+
+
 def test_nonfinite_initial_state_rejected(lib):
     solid = np.zeros((3, 3, 3), np.uint8)
     u = np.zeros((3, 3, 3, 3))

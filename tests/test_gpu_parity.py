@@ -114,6 +114,26 @@ def test_small_random_reduced(q, prec, dims):
     sim.close()
 
 
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("dims", [(1 << 20, 1, 1), (1, 1 << 20, 1), (1, 1, 1 << 20)])
+def test_longest_extent(prec, dims):
+    """The largest extent one axis may have (2^20 nodes), along each axis."""
+    nx, ny, nz = dims
+    solid, drho, u = inputs.random_state(nx, ny, nz, seed=4100 + (nx > 1) + 2 * (ny > 1))
+    g = (1e-5, -2e-5, 3e-6)
+    print(f"[case] longest extent {prec} dims={dims}", flush=True)
+    sim, out = run_gpu([(solid, drho, u)], 19, prec, g, 4)
+    sim.close()
+    ref = run_oracle(19, solid, drho, u, g, 4)
+    if prec == "f64":
+        assert_f64_parity(out[0], ref, solid)
+    else:
+        err = reduced_errors(out[0], ref, solid)
+        print(f"[err] {prec} {dims} {err}", flush=True)
+        for key, bound in reduced_bounds(prec, np.abs(u).max()).items():
+            assert err[key] <= bound, (key, err[key], bound)
+
+
 def test_graph_replay_equals_single_launches():
     solid, drho, u = inputs.random_state(20, 12, 9, seed=77)
     g = (1e-5, 0, 0)
