@@ -55,6 +55,26 @@ def test_512_cube_porosity06_16bit(prec):
         check_step(sim, 0, geo.solid, 19, prec, g, idx, f"{prec} tile {sim.info()['tile']}")
 
 
+def test_arrays_beyond_32bit_offsets():
+    """512 x 512 x 2048 (537M nodes): each FP32 state array is larger than the
+    z-march kernels' 32-bit buffer offsets reach, so the context runs the
+    per-node gather kernel on the dense layout (64-bit indexing)."""
+    geo = inputs.spheres(512, 512, 2048, 12.0, 0.7, seed=3100)
+    g = (1e-5, -2e-6, 3e-6)
+    print("[case] 512x512x2048 porosity 0.7 D3Q19 f32", flush=True)
+    with tau1.Sim([tau1.Sample(geo.solid)], lattice=19, precision="f32", g=g,
+                  graph_chunk=100) as sim:
+        sim.autotune(2)
+        inf = sim.info()
+        assert inf["kernel"] == 0 and inf["layout"] == 0
+        sim.step(3)
+        idx = sample_nodes(geo.solid, 20000, seed=11)
+        check_step(sim, 0, geo.solid, 19, "f32", g, idx, "512x512x2048 gather")
+        k, mass = sim.permeability(0, 0)
+    assert abs(mass - geo.n_fluid) <= 1e-9 * geo.n_fluid
+    assert np.isfinite(k) and k > 0
+
+
 def test_batch_of_64_samples():
     """Batched workload: 64 uneven samples in one context, sampled per sample."""
     batch = inputs.batch_recipe(64, 5000, workers=8)
