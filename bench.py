@@ -33,8 +33,9 @@ Sections (``--sections``, default all):
              1 % over 10000 steps.
   porosity   D3Q19 FP32 on 256^3 sphere packings (r = 8, target porosity 0.05,
              0.1, 0.2, 0.3, 0.5, 0.6, 0.7, 0.8, 0.9, seeds 2000+i), 1000 steps
-             each, packed and dense state layouts, permeability, work items
-             visited, and the chunk statistics of the paper's bandwidth model
+             each: the z-march on the packed and the dense state layouts and
+             the gather over the fluid-node list (kernel 3); permeability,
+             work items visited, and the chunk statistics of the paper's bandwidth model
              for porous media (fraction of lane chunks stored, mean porosity of
              the stored chunks, share of mixed chunks).
 The oracle leg (``cpu_baseline``) times the FP64 CPU oracle on a few steps of
@@ -206,8 +207,9 @@ class GpuRunner:
         return wall, ev
 
     def case(self, samples, lattice, precision, steps, warmup, graph_chunk, tile,
-             g=G_MAIN, label="", layout=-1, repeats=1):
-        sim = self.make(samples, lattice, precision, g, graph_chunk, tile, layout=layout)
+             g=G_MAIN, label="", layout=-1, repeats=1, kernel=-1):
+        sim = self.make(samples, lattice, precision, g, graph_chunk, tile, kernel=kernel,
+                        layout=layout)
         wall, ev = self.time_steps(sim, steps, warmup)
         inf = sim.info()
         walls = [wall] + [self.time_steps(sim, steps, 0)[0] for _ in range(repeats - 1)]
@@ -354,15 +356,16 @@ def porosity_section(gr, geos, args, out):
     rows = []
     for phi, geo in zip(POROSITIES, geos):
         row = {"target": phi, "porosity": geo.porosity, "spheres": geo.spheres}
-        for layout, name in ((1, "packed"), (0, "dense")):
+        for layout, kernel, name in ((1, -1, "packed"), (0, -1, "dense"),
+                                     (0, 3, "fluid_list")):
             sim, res = gr.case([tau1.Sample(geo.solid)], 19, "f32", args.porosity_steps,
                                args.warmup, args.graph_chunk, -1,
-                               label=f"porosity {phi} {name}", layout=layout)
+                               label=f"porosity {phi} {name}", layout=layout, kernel=kernel)
             if layout == 1:
                 row["k"], row["mass"] = sim.permeability(0, 0)
             sim.close()
             row[name] = {key: res[key] for key in ("gflups", "alg_gbs", "frac", "tile",
-                                                   "launch_ms", "work_items")}
+                                                   "kernel", "launch_ms", "work_items")}
         row.update(chunk_stats(geo.solid, 4))
         # bytes the packed layout moves per step: state of the stored chunks read
         # and written once, as a rate over the measured launch time

@@ -102,7 +102,13 @@ typedef struct {
     void *workspace;        /* borrowed device memory, 256-byte aligned         */
     size_t workspace_bytes;
     int32_t kernel;         /* step kernel: -1 = automatic (tuned or default),
-                               0 = per-node gather, 1 = z-march tiles          */
+                               0 = per-node gather, 1 = z-march tiles,
+                               3 = per-node gather over lists of the fluid
+                               nodes (one thread per fluid node: for media
+                               of low porosity; dense layout, 4 bytes of
+                               list per fluid node; TAU1_E_UNSUPPORTED with
+                               layout 1, on D2Q9 or for a sample of more
+                               than 2^32 nodes; never chosen automatically) */
     int32_t tile;           /* z-march tile shape, -1 = automatic; 0-15 =
                                z-segment of 16/32/64/128 planes (tile % 4) x
                                load schedule (tile / 4: 0 just in time,
@@ -132,7 +138,7 @@ typedef struct {
 typedef struct {
     int32_t lattice, precision, n_samples;
     int32_t kernel;          /* step kernel in use: 0 per-node gather,
-                                1 z-march tiles, 2 D2Q9                      */
+                                1 z-march tiles, 2 D2Q9, 3 fluid-list gather */
     int32_t tile;            /* tile shape index in use (z-march)           */
     int32_t graph_chunk;
     int32_t layout;          /* 1 if any sample is stored packed, else 0    */
@@ -178,7 +184,8 @@ tau1_status tau1_permeability(tau1_ctx *ctx, int32_t sample,
 
 /* Times each eligible step-kernel shape for trial_steps steps (state is not
  * advanced: trials write only the spare buffer), keeps the fastest and, if
- * the descriptor named a cache file, records it there.  Synchronous. */
+ * the descriptor named a cache file, records it there.  Synchronous.  A
+ * context created with kernel 3 keeps it (no shapes to choose from). */
 tau1_status tau1_autotune(tau1_ctx *ctx, int32_t trial_steps);
 
 tau1_status tau1_get_info(const tau1_ctx *ctx, tau1_info *info);

@@ -15,6 +15,7 @@
 #include "../../include/tau1.h"
 #include "tau1_device.hpp"
 #include "tau1_kernels.hpp"
+#include "tau1_list.hpp"
 #include "tau1_zmarch.hpp"
 #include "tau1_service.hpp"
 
@@ -31,6 +32,7 @@ size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 struct SampleHost {
     SampleDev dev;
     int64_t n_fluid;
+    int64_t list_nf = 0;         // fluid-list kernel: fluid nodes listed
     std::vector<uint32_t> ctab;  // packed layout: chunk table (4 words per entry)
     std::vector<uint8_t> rowfluid;  // z-march samples: 1 if row y + ny z holds a fluid node
 };
@@ -42,6 +44,9 @@ struct Plan {
     size_t tiles_off = 0;     // z-march work list
     size_t stage_off = 0;     // upload / readback staging
     size_t stage_bytes = 0;
+    size_t list_dev_off = 0;  // fluid-list kernel: ListDev[nsamples]
+    std::vector<ListDev> lists;  // fluid-list kernel: per-sample lists
+    int64_t list_blocks = 0;     // blocks of one fluid-list launch
     size_t total = 0;
     int64_t ntiles = 0;
     int64_t total_blocks = 0;
@@ -49,6 +54,9 @@ struct Plan {
     bool pack_refused = false; // packed layout requested but no sample qualifies
     std::vector<SampleHost> s;
 };
+
+// Step kernel 3: the per-node gather over lists of the fluid nodes.
+constexpr int kListKernel = 3;
 
 bool valid_lattice(int q) { return q == 9 || q == 15 || q == 19 || q == 27; }
 bool valid_precision(int p) { return p >= kF64 && p <= kBF16; }
@@ -58,7 +66,9 @@ tau1_status validate(const tau1_desc* d) {
     if (!valid_lattice(d->lattice) || !valid_precision(d->precision)) return TAU1_E_INVALID;
     if (d->n_samples < 1 || d->n_samples > kMaxSamples || !d->samples) return TAU1_E_INVALID;
     if (d->graph_chunk < 0 || (d->graph_chunk % 2) != 0) return TAU1_E_INVALID;
-    if (d->kernel < -1 || d->kernel > 1) return TAU1_E_INVALID;
+    if (d->kernel < -1 || d->kernel > 1) {
+        if (d->kernel != kListKernel) return TAU1_E_INVALID;
+    }
     if (d->tile < -1 || d->tile >= kNumTiles) return TAU1_E_INVALID;
     if (d->layout < -1 || d->layout > 1) return TAU1_E_INVALID;
     if (d->x_boundary < 0 || d->x_boundary > 1) return TAU1_E_INVALID;
@@ -90,6 +100,14 @@ tau1_status validate(const tau1_desc* d) {
 // one kernel, in FP64 and FP32; its boundaries exist only there.
 tau1_status unsupported(const tau1_desc* d) {
     if (d->lattice == 9 && (d->precision > kF32 || d->kernel != -1)) return TAU1_E_UNSUPPORTED;
+    if (d->kernel == kListKernel) {
+        // dense layout only; node indices are 32-bit
+        if (d->layout == 1) return TAU1_E_UNSUPPORTED;
+        for (int i = 0; i < d->n_samples; ++i) {
+            const tau1_sample& s = d->samples[i];
+            if (s.nx * s.ny * s.nz > (int64_t(1) << 32)) return TAU1_E_UNSUPPORTED;
+        }
+    }
     if (d->lattice != 9 && (d->x_boundary != 0 || d->wall_u[0] != 0.0 || d->wall_u[1] != 0.0 ||
                             d->wall_u[2] != 0.0))
         return TAU1_E_UNSUPPORTED;
@@ -160,7 +178,8 @@ Plan make_plan(const tau1_desc* d, bool tables) {
     // where the z-march kernel runs
     const bool zm = zmarch_supported(d->lattice, d->precision, p.s.data(), d->n_samples);
     const bool auto_pack = d->precision == kF32 && (d->tile < 0 || tile_mode(d->tile) == 3);
-    const bool pack = zm && d->kernel != 0 && (d->layout == 1 || (d->layout < 0 && auto_pack));
+    const bool pack = zm && (d->kernel == -1 || d->kernel == 1) &&
+                      (d->layout == 1 || (d->layout < 0 && auto_pack));
     // All samples of one lane layout share a launch, so a layout is packed
     // only if each of its samples fits: the step kernel addresses the four
     // packed arrays of a buffer with 32-bit offsets from one base.
@@ -220,6 +239,26 @@ Plan make_plan(const tau1_desc* d, bool tables) {
             off = align_up(off + (size_t)4 * sd.stride * sz, kAlign);
         }
     }
+    if (d->kernel == kListKernel) {
+        // fluid-node lists (uint32 node indices) and their descriptors
+        p.list_dev_off = off;
+        off = align_up(off + sizeof(ListDev) * d->n_samples, kAlign);
+        p.lists.resize(d->n_samples);
+        int64_t fb = 0;
+        for (int i = 0; i < d->n_samples; ++i) {
+            const tau1_sample& in = d->samples[i];
+            const int64_t n = in.nx * in.ny * in.nz;
+            int64_t nf = 0;
+            for (int64_t j = 0; j < n; ++j) nf += in.solid[j] ? 0 : 1;
+            p.s[i].list_nf = nf;
+            p.lists[i].list = (int64_t)off;
+            p.lists[i].nf = nf;
+            p.lists[i].fblock0 = fb;
+            fb += (nf + kGatherBlock - 1) / kGatherBlock;
+            off = align_up(off + sizeof(uint32_t) * (size_t)std::max<int64_t>(nf, 1), kAlign);
+        }
+        p.list_blocks = fb;
+    }
     const int64_t stage_nodes = std::min<int64_t>(maxn, kStageNodes);
     p.stage_off = off;
     // solid byte + drho + 3 u (FP64) on upload; 4 FP64 on readback
@@ -253,6 +292,9 @@ struct tau1_ctx {
         StepArgs args[2];
     };
     std::vector<ZGroup> zgroups;
+    // fluid-list kernel: device address of the ListDev array (its second
+    // argument; the other kernels take one argument and ignore it)
+    const ListDev* list_dev = nullptr;
     int parity = 0;
     int64_t steps_done = 0;
     int64_t n_nodes = 0, n_fluid = 0;
@@ -279,6 +321,27 @@ tau1_status fail_hip(tau1_ctx* ctx, hipError_t e) {
 // --- kernel dispatch -------------------------------------------------------
 template <int Q, int P>
 void* gather_fn() { return reinterpret_cast<void*>(&k_gather<Q, P>); }
+
+template <int Q, int P>
+void* gather_list_fn() { return reinterpret_cast<void*>(&k_gather_list<Q, P>); }
+
+void* pick_gather_list(int q, int p) {
+    switch (q * 10 + p) {
+        case 150: return gather_list_fn<15, kF64>();
+        case 151: return gather_list_fn<15, kF32>();
+        case 152: return gather_list_fn<15, kF16>();
+        case 153: return gather_list_fn<15, kBF16>();
+        case 190: return gather_list_fn<19, kF64>();
+        case 191: return gather_list_fn<19, kF32>();
+        case 192: return gather_list_fn<19, kF16>();
+        case 193: return gather_list_fn<19, kBF16>();
+        case 270: return gather_list_fn<27, kF64>();
+        case 271: return gather_list_fn<27, kF32>();
+        case 272: return gather_list_fn<27, kF16>();
+        case 273: return gather_list_fn<27, kBF16>();
+    }
+    return nullptr;
+}
 
 void* pick_gather(int q, int p) {
     switch (q * 10 + p) {
@@ -319,7 +382,8 @@ void* pick_d2q9(int p) {
 }
 
 // Launch geometry of one step kernel: z-march group g (kernel 1), the
-// per-node gather over every sample (kernel 0) or the D2Q9 kernel (2).
+// per-node gather over every sample (kernel 0), the D2Q9 kernel (2) or the
+// gather over the fluid-node lists (3).
 Launch step_launch(const tau1_ctx* ctx, int kernel, int tile, int g) {
     Launch l{};
     if (kernel == 1) {
@@ -329,6 +393,11 @@ Launch step_launch(const tau1_ctx* ctx, int kernel, int tile, int g) {
         l.fn = pick_zmarch(ctx->lattice, ctx->precision, grp.variant, mode);
         l.block = dim3(zmarch_threads(tile));
         l.grid = dim3((unsigned)zmarch_grid(grp.args[0].ntiles, tile));
+        l.shmem = 0;
+    } else if (kernel == kListKernel) {
+        l.fn = pick_gather_list(ctx->lattice, ctx->precision);
+        l.block = dim3(kGatherBlock);
+        l.grid = dim3((unsigned)ctx->plan.list_blocks);
         l.shmem = 0;
     } else {
         l.fn = kernel == 2 ? pick_d2q9(ctx->precision) : pick_gather(ctx->lattice, ctx->precision);
@@ -353,7 +422,7 @@ tau1_status launch_one(tau1_ctx* ctx, int kernel, int tile, int parity) {
         const Launch l = step_launch(ctx, kernel, tile, g);
         if (!l.fn) return TAU1_E_UNSUPPORTED;
         if (l.grid.x == 0) continue;
-        void* params[] = {launch_args(ctx, kernel, g, parity)};
+        void* params[] = {launch_args(ctx, kernel, g, parity), &ctx->list_dev};
         HIP_TRY(hipLaunchKernel(l.fn, l.grid, l.block, params, l.shmem, ctx->stream));
     }
     return TAU1_OK;
@@ -382,7 +451,8 @@ tau1_status build_graph(tau1_ctx* ctx) {
         if (l.grid.x == 0) continue;
         hipGraphNode_t prev = nullptr;
         for (int s = 0; s < ctx->graph_chunk; ++s) {
-            void* params[] = {launch_args(ctx, ctx->kernel, g, (ctx->parity + s) & 1)};
+            void* params[] = {launch_args(ctx, ctx->kernel, g, (ctx->parity + s) & 1),
+                              &ctx->list_dev};
             hipKernelNodeParams kp{};
             kp.func = l.fn;
             kp.gridDim = l.grid;
@@ -636,6 +706,48 @@ tau1_status check_usable(const tau1_ctx* ctx) {
 // ===========================================================================
 // C ABI
 // ===========================================================================
+namespace {
+
+// Fluid-node lists of the fluid-list kernel: node indices in increasing
+// order, built on the host and copied in pieces, then the per-sample
+// descriptors.
+tau1_status upload_lists(tau1_ctx* ctx, const tau1_desc* d) {
+    std::vector<uint32_t> buf;
+    try {
+        buf.resize((size_t)kStageNodes);
+    } catch (const std::bad_alloc&) {
+        return TAU1_E_NOMEM;
+    }
+    const int64_t piece = (int64_t)buf.size();
+    for (int i = 0; i < d->n_samples; ++i) {
+        const tau1_sample& in = d->samples[i];
+        const int64_t n = in.nx * in.ny * in.nz;
+        const ListDev& l = ctx->plan.lists[i];
+        int64_t written = 0, fill = 0;
+        for (int64_t j = 0; j <= n; ++j) {
+            if (j < n && !in.solid[j]) buf[(size_t)fill++] = (uint32_t)j;
+            if (fill == piece || (j == n && fill > 0)) {
+                if (written + fill > l.nf) return TAU1_E_INVALID;  // solid changed under us
+                HIP_TRY(hipMemcpyAsync(ctx->base + l.list + sizeof(uint32_t) * written,
+                                       buf.data(), sizeof(uint32_t) * (size_t)fill,
+                                       hipMemcpyHostToDevice, ctx->stream));
+                HIP_TRY(hipStreamSynchronize(ctx->stream));  // buf is refilled next
+                written += fill;
+                fill = 0;
+            }
+        }
+        if (written != l.nf) return TAU1_E_INVALID;
+    }
+    HIP_TRY(hipMemcpyAsync(ctx->base + ctx->plan.list_dev_off, ctx->plan.lists.data(),
+                           sizeof(ListDev) * ctx->plan.lists.size(), hipMemcpyHostToDevice,
+                           ctx->stream));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    ctx->list_dev = reinterpret_cast<const ListDev*>(ctx->base + ctx->plan.list_dev_off);
+    return TAU1_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 const char* tau1_strerror(tau1_status s) {
@@ -781,6 +893,7 @@ tau1_status tau1_create(const tau1_desc* desc, tau1_ctx** out) {
     }
     for (int i = 0; st == TAU1_OK && i < ctx->nsamples; ++i)
         st = upload_sample(ctx, i, desc->samples[i]);
+    if (st == TAU1_OK && desc->kernel == kListKernel) st = upload_lists(ctx, desc);
     if (st != TAU1_OK) {
         delete ctx;
         return st;
@@ -886,6 +999,7 @@ tau1_status tau1_autotune(tau1_ctx* ctx, int32_t trial_steps) {
     tau1_status st = check_usable(ctx);
     if (st != TAU1_OK) return st;
     if (trial_steps < 1) return TAU1_E_INVALID;
+    if (ctx->kernel == kListKernel) return TAU1_OK;  // no shapes to choose from
     if (!zmarch_eligible(ctx)) return TAU1_OK;  // only the gather kernel applies
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0));

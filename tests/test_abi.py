@@ -144,3 +144,34 @@ def test_null_context_calls(lib):
     assert lib.tau1_step(None, 1) == tau1.TAU1_E_INVALID
     assert lib.tau1_sync(None) == tau1.TAU1_E_INVALID
     lib.tau1_destroy(None)                    # NULL-safe
+
+
+def test_fluid_list_kernel_workspace():
+    """Kernel 3 adds, to the dense layout, one uint32 index per fluid node per
+    sample and one 24-byte descriptor per sample (256-byte aligned pieces)."""
+    def align(v):
+        return (v + 255) // 256 * 256
+    a = inputs.random_state(40, 6, 5, seed=77, solid_frac=0.8)[0]
+    b = inputs.random_state(64, 3, 2, seed=78, solid_frac=0.3)[0]
+    dense = tau1.workspace_size([(a,), (b,)], kernel=0)
+    listed = tau1.workspace_size([(a,), (b,)], kernel=3)
+    extra = align(24 * 2) + align(4 * int((a == 0).sum())) + align(4 * int((b == 0).sum()))
+    assert listed == dense + extra
+    # an all-solid sample still gets one (unused) slot
+    s = np.ones((2, 2, 2), np.uint8)
+    assert tau1.workspace_size([(s,)], kernel=3) == \
+        tau1.workspace_size([(s,)], kernel=0) + align(24) + align(4)
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(kernel=3, layout=1), tau1.TAU1_E_UNSUPPORTED),   # dense layout only
+    (dict(kernel=3, lattice=9), tau1.TAU1_E_UNSUPPORTED),  # 3-D lattices only
+    (dict(kernel=2), tau1.TAU1_E_INVALID),                 # 2 is the D2Q9 kernel's own
+    (dict(kernel=4), tau1.TAU1_E_INVALID),
+])
+def test_fluid_list_kernel_requests(lib, kw, status):
+    solid = np.zeros((1, 4, 8), np.uint8)
+    d, keep = tau1._desc([tau1.Sample(solid)], kw.get("lattice", 19), "f32", (0, 0, 0), 0,
+                         kw["kernel"], -1, (0, 0), None, kw.get("layout", -1))
+    n = ctypes.c_size_t(0)
+    assert lib.tau1_workspace_size(ctypes.byref(d), ctypes.byref(n)) == status
