@@ -4,7 +4,7 @@
  * runs.
  *
  * TEST INFRASTRUCTURE ONLY.  Nothing in the product library links, loads or
- * calls this file; only the test suite and the benchmark's checks do.  It
+ * calls this file; only the test suite does.  It
  * shares no source, header, table or helper with the GPU path.
  *
  * What it computes (Bacza, Tomczak, Matyka, "The lattice Boltzmann method for
