@@ -195,7 +195,8 @@ class Sim:
     """One Tau1 context over one or more samples (batched when several).
 
     ``precision`` is one of "f64", "f32", "f16", "bf16".  ``kernel`` -1 picks
-    automatically, 0 forces the per-node gather kernel, 1 the z-march tiles.
+    automatically, 0 forces the per-node gather kernel, 1 the z-march tiles,
+    3 the per-node gather over a list of the fluid nodes (dense layout).
     ``layout`` -1 picks the state layout automatically, 0 is dense, 1 packed
     (all-solid lane chunks not stored).  ``lattice=9`` is the D2Q9 validation
     lattice (samples of shape (1, ny, nx); solid values 0 fluid, 1 wall,
