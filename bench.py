@@ -80,13 +80,16 @@ def parse_args(argv=None):
                     help="timed regions of --steps steps for the main workload; the first "
                          "gives the headline value, all of them the median and spread")
     ap.add_argument("--sections", default="main,lattices,precision,batch,porosity,validation")
-    ap.add_argument("--tile", type=int, default=-1, help="z-march tile; -1 = autotune")
+    ap.add_argument("--tile", type=int, default=-1,
+                    help="z-march tile of the main and batch sections; -1 = autotune")
     ap.add_argument("--graph-chunk", type=int, default=100)
     ap.add_argument("--lattice-steps", type=int, default=500)
     ap.add_argument("--precision-steps", type=int, default=2000)
     ap.add_argument("--batch-steps", type=int, default=1000)
     ap.add_argument("--porosity-steps", type=int, default=1000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batch-solo", action="store_true",
+                    help="batch section: skip the one-by-one runs (for profiling)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run the copy kernel (for counter calibration)")
     return ap.parse_args(argv)
@@ -288,11 +291,14 @@ def batch_section(gr, batch, args, out):
     from paper_2312_14742_amd import tau1
     samples = [tau1.Sample(b.geometry.solid) for b in batch]
     steps = args.batch_steps
-    sim, res = gr.case(samples, 19, "f32", steps, args.graph_chunk, args.graph_chunk, -1,
-                       label="batched 64 samples")
+    sim, res = gr.case(samples, 19, "f32", steps, args.graph_chunk, args.graph_chunk,
+                       args.tile, label="batched 64 samples")
     probe = [0, max(range(len(batch)), key=lambda i: batch[i].side)]
     batched_state = {i: sim.moments(i) for i in probe}
     sim.close()
+    if args.no_batch_solo:
+        out["batched"] = res
+        return
     solo_time = 0.0
     solo_ev = 0.0
     nf_total = 0
