@@ -55,6 +55,48 @@ def test_512_cube_porosity06_16bit(prec):
         check_step(sim, 0, geo.solid, 19, prec, g, idx, f"{prec} tile {sim.info()['tile']}")
 
 
+@pytest.mark.parametrize("transform", ["mirror_x", "permute_axes"])
+def test_512_cube_symmetry(transform):
+    """A property that holds at any size, checked at the full size where the
+    oracle cannot follow many steps: running the x-mirrored, or the
+    axis-permuted ((x, y, z) -> (y, z, x)), copy of the headline workload
+    gives the mirrored or permuted result.  The two runs round their sums in
+    different orders, so they agree to FP32 rounding: rel-L2(u) within
+    steps x 2 x 2^-24 and drho within that times max|u|."""
+    geo = inputs.spheres(512, 512, 512, 12.0, 0.7, seed=3000)
+    drho, u = random_fields(geo.solid, seed=43)
+    g = (1e-6, 2e-7, -3e-7)
+    steps = 20
+    if transform == "mirror_x":
+        tf = lambda a: np.ascontiguousarray(a[:, :, ::-1])        # noqa: E731
+        ut = np.stack([-tf(u[0]), tf(u[1]), tf(u[2])])
+        gt = (-g[0], g[1], g[2])
+        back = lambda uu: np.stack([-tf(uu[0]), tf(uu[1]), tf(uu[2])])  # noqa: E731
+    else:
+        tf = lambda a: np.ascontiguousarray(a.transpose(2, 0, 1))  # noqa: E731
+        ut = np.stack([tf(u[1]), tf(u[2]), tf(u[0])])
+        gt = (g[1], g[2], g[0])
+        back = lambda uu: np.stack([tf(uu[1]), tf(uu[2]), tf(uu[0])])  # noqa: E731
+    print(f"[case] 512^3 porosity 0.7 f32 {transform}", flush=True)
+    res = []
+    for solid, d0, u0, gg in ((geo.solid, drho, u, g), (tf(geo.solid), tf(drho), ut, gt)):
+        with tau1.Sim([tau1.Sample(solid, d0, u0)], lattice=19, precision="f32", g=gg,
+                      graph_chunk=10) as sim:
+            sim.autotune(3)
+            assert sim.info()["kernel"] == 1
+            sim.step(steps)
+            res.append(sim.moments(0))
+    (d_a, u_a), (d_b, u_b) = res
+    fl = tf(geo.solid) == 0
+    want_u = back(u_a)
+    eu = float(np.sqrt(np.sum((u_b - want_u)[:, fl] ** 2) / np.sum(want_u[:, fl] ** 2)))
+    ed = float(np.abs(d_b - tf(d_a)).max())
+    bound = steps * 2.0 * 2.0 ** -24
+    print(f"[err] {transform}: rel-L2(u) {eu:.3e}, max|ddrho| {ed:.3e}", flush=True)
+    assert eu <= bound
+    assert ed <= bound * np.abs(u_a).max()
+
+
 def test_arrays_beyond_32bit_offsets():
     """512 x 512 x 2048 (537M nodes): each FP32 state array is larger than the
     z-march kernels' 32-bit buffer offsets reach, so the context runs the
