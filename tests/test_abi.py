@@ -175,3 +175,13 @@ def test_fluid_list_kernel_requests(lib, kw, status):
                          kw["kernel"], -1, (0, 0), None, kw.get("layout", -1))
     n = ctypes.c_size_t(0)
     assert lib.tau1_workspace_size(ctypes.byref(d), ctypes.byref(n)) == status
+
+
+def test_fluid_list_kernel_rejects_more_than_2_32_nodes(lib):
+    """Node indices of the lists are 32-bit (checked before the mask is read;
+    a small array stands in for the large one)."""
+    d, keep = tau1._desc([tau1.Sample(np.zeros((2, 2, 2), np.uint8))], 19, "f32", (0, 0, 0), 0,
+                         3, -1, (0, 0), None, -1)
+    keep[0].nz, keep[0].ny, keep[0].nx = 3, 1 << 11, 1 << 20
+    n = ctypes.c_size_t(0)
+    assert lib.tau1_workspace_size(ctypes.byref(d), ctypes.byref(n)) == tau1.TAU1_E_UNSUPPORTED
