@@ -174,3 +174,22 @@ def test_reductions_vs_oracle(prec):
     assert abs(k - kref) <= tol * abs(kref), (k, kref)
     assert abs(m - mref) <= 1e-12 * mref if prec == "f64" else abs(m - mref) <= 1e-6 * mref
     sim.close()
+
+
+@pytest.mark.parametrize("kernel,prec", [(0, "f64"), (1, "f32"), (3, "f32"), (1, "bf16")])
+def test_runs_are_deterministic(kernel, prec):
+    """Two contexts over the same inputs give the same bits: state, mass and
+    permeability (no atomics in the step; the reductions use a fixed tree)."""
+    geo = inputs.spheres(64, 48, 40, 5.0, 0.6, seed=31)
+    g = (1e-5, 2e-6, 0.0)
+    print(f"[case] determinism kernel={kernel} {prec}", flush=True)
+    res = []
+    for _ in range(2):
+        with tau1.Sim([tau1.Sample(geo.solid)], lattice=19, precision=prec, g=g,
+                      kernel=kernel, layout=0 if kernel == 3 else -1, graph_chunk=10) as sim:
+            sim.step(37)
+            d, u = sim.moments(0)
+            k, m = sim.permeability(0, 0)
+            res.append((d.tobytes(), u.tobytes(), np.float64(k).tobytes(),
+                        np.float64(m).tobytes()))
+    assert res[0] == res[1]
