@@ -35,11 +35,11 @@ Sections (``--sections``, default all):
              0.1, 0.2, 0.3, 0.5, 0.6, 0.7, 0.8, 0.9, seeds 2000+i), 1000 steps
              each: the z-march on the packed and the dense state layouts and
              the gather over the fluid-node list (kernel 3); permeability,
-             work items visited, and the chunk statistics of the paper's bandwidth model
-             for porous media (fraction of lane chunks stored, mean porosity of
-             the stored chunks, share of mixed chunks).
-The oracle leg (``cpu_baseline``) times the FP64 CPU oracle on a few steps of
-the main workload on the host cores.
+             work items visited, and the chunk statistics of the paper's
+             bandwidth model for porous media (fraction of lane chunks stored,
+             mean porosity of the stored chunks, share of mixed chunks).
+The oracle leg (``cpu_baseline``) times the FP64 CPU oracle on about 15 s of
+steps of the main workload on the host cores.
 
 Prints ONE JSON line on stdout; progress goes to stderr.  Only one GPU is
 used: ``--gpus`` above 1 exits with a message.
@@ -81,7 +81,8 @@ def parse_args(argv=None):
                          "gives the headline value, all of them the median and spread")
     ap.add_argument("--sections", default="main,lattices,precision,batch,porosity,validation")
     ap.add_argument("--tile", type=int, default=-1,
-                    help="z-march tile of the main and batch sections; -1 = autotune")
+                    help="z-march tile of the main, lattices and batch sections; "
+                         "-1 = autotune")
     ap.add_argument("--graph-chunk", type=int, default=100)
     ap.add_argument("--lattice-steps", type=int, default=500)
     ap.add_argument("--precision-steps", type=int, default=2000)
@@ -492,7 +493,7 @@ def main(argv=None):
         sweep = {}
         for q in (15, 27):
             sim, r = gr.case([tau1.Sample(geos["main"].solid)], q, "f32", args.lattice_steps,
-                             args.warmup, args.graph_chunk, -1, label=f"D3Q{q} f32")
+                             args.warmup, args.graph_chunk, args.tile, label=f"D3Q{q} f32")
             sim.close()
             sweep[f"D3Q{q}"] = r
         if main_res is not None:
