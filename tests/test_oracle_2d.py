@@ -158,6 +158,68 @@ def test_lid_driven_cavity_mass_mirror_and_circulation():
     assert a.u[0][n // 3, mid] < 0.0        # return flow lower down
 
 
+def two_node_2d_error(axis: int) -> float:
+    """Deviation of one D2Q9 step on a periodic two-node lattice (two nodes
+    along `axis`, one across) from the moment closed form of the 3-D pin:
+    drho'(0) = (2/3) drho_0 + (1/3) drho_1 + rho_1 v_a^2 and the mirror
+    value at node 1, j'(0) = rho_1 (v_a, v_b / 3), j'(1) = rho_1 (0, 2 v_b / 3),
+    with v = 0 at node 0 and g = 0.  It rests on the D2Q9 equilibrium's
+    momentum flux rho/3 I + rho v v, its third moment rho v_b / 3 and the
+    c_a != 0 weights adding up to 1/3."""
+    shape = (1, 2) if axis == 0 else (2, 1)     # (ny, nx)
+    d0, d1 = 3.0e-3, -2.0e-3
+    v1 = np.array([0.029, -0.021])
+    i0 = (0, 0)
+    i1 = (0, 1) if axis == 0 else (1, 0)
+    drho = np.zeros(shape)
+    u = np.zeros((2,) + shape)
+    drho[i0], drho[i1] = d0, d1
+    u[(0,) + i1], u[(1,) + i1] = v1
+    out = oracle.run_2d(oracle.State2D(np.zeros(shape, np.uint8), drho, u), 1)
+    rho1 = 1.0 + d1
+    va2 = v1[axis] ** 2
+    across = np.arange(2) != axis
+    err = max(abs(out.drho[i0] - ((2.0 / 3.0) * d0 + d1 / 3.0 + rho1 * va2)),
+              abs(out.drho[i1] - ((2.0 / 3.0) * d1 + d0 / 3.0 - rho1 * va2)))
+    for idx, want in ((i0, rho1 * np.where(across, v1 / 3.0, v1)),
+                      (i1, rho1 * np.where(across, 2.0 * v1 / 3.0, 0.0))):
+        j = np.array([out.u[(b,) + idx] for b in range(2)]) * (1.0 + out.drho[idx])
+        err = max(err, np.abs(j - want).max())
+    return float(err)
+
+
+@pytest.mark.parametrize("axis", (0, 1))
+def test_two_node_second_and_third_moments_d2q9(axis):
+    assert two_node_2d_error(axis) <= 1e-16
+
+
+def couette_error(ny: int, lid_u: float, steps: int) -> float:
+    """Plane Couette flow: a resting wall at y = 0, a lid at y = ny - 1 moving
+    along x with lid_u, periodic x.  With halfway bounce-back the walls sit
+    half a node beyond the outer fluid rows, a distance ny - 2 apart, and the
+    steady profile is the straight line u_x(y) = lid_u (y - 1/2) / (ny - 2)
+    through the no-slip wall and the lid speed, with rho = 1 and u_y = 0.  The
+    moving-wall rule must hand the fluid exactly the lid's momentum; a wrong
+    amplitude of its 6 w_k rho (c_k . u_w) term scales the whole line.
+    Returns the largest deviation relative to lid_u."""
+    t = np.zeros((ny, 3), np.uint8)
+    t[0] = 1
+    t[-1] = 2
+    a = oracle.run_2d(oracle.State2D(t), steps, uw=(lid_u, 0.0))
+    y = np.arange(1, ny - 1)
+    want = lid_u * (y - 0.5) / (ny - 2)
+    err = max(np.abs(a.u[0][1:-1] - want[:, None]).max(), np.abs(a.u[1]).max(),
+              np.abs(a.drho).max())
+    return float(err / abs(lid_u))
+
+
+def test_couette_profile_of_the_moving_wall():
+    # the slowest mode of 8 fluid rows decays by e in ~40 steps: 3000 steps
+    # reach the steady line to FP64 rounding
+    assert couette_error(10, 0.05, 3000) <= 1e-13
+    assert couette_error(10, -0.02, 3000) <= 1e-13
+
+
 def test_rest_state_with_all_boundaries_stays_zero():
     t = np.zeros((10, 16), np.uint8)
     t[0] = 1

@@ -37,6 +37,13 @@ MUTANTS = {
     "opposite_map": [("(k % 2 ? k + 1 : k - 1)", "(k % 2 ? k : k - 1)", 1)],
     "zou_he_rebuild_bgk": [("fi[1] = fi[2] + (2.0 / 3.0) * ru;", "fi[1] = fi[2] + (1.0 / 3.0) * ru;", 1)],
     "pull_from_wrong_side": [("long sx = x - C9[k][0];", "long sx = x + C9[k][0];", 1)],
+    # amplitude of the moving wall's momentum, in both forms (only the
+    # Couette profile sees it)
+    "moving_wall_amplitude_both": [("f += 6.0 * W9[k]", "f += 3.0 * W9[k]", 1),
+                                   ("fi[k] += 6.0 * W9[k]", "fi[k] += 3.0 * W9[k]", 1)],
+    # the O(u^2) part of Eq. (3), shared by both forms
+    "quadratic_doubled": [("(4.5 * cu) * cu) - 1.5 * vv;", "(9.0 * cu) * cu) - 3.0 * vv;", 1)],
+    "quadratic_dropped": [("(3.0 * cu + (4.5 * cu) * cu) - 1.5 * vv;", "(3.0 * cu);", 1)],
 }
 
 
@@ -112,8 +119,18 @@ def _quick_pins():
         return (abs(m - (t == 0).sum()) <= 1e-12 * (t == 0).sum()
                 and a.u[0][n - 2, n // 2] > 0.01 and a.u[0][n // 3, n // 2] < 0.0)
 
+    def two_node_ok():
+        from test_oracle_2d import two_node_2d_error
+        return max(two_node_2d_error(0), two_node_2d_error(1)) <= 1e-16
+
+    def couette_ok():
+        from test_oracle_2d import couette_error
+        return couette_error(6, 0.05, 600) <= 1e-12
+
     check("lattice", lattice_ok)
     check("bgk_bitwise", bitwise_ok)
+    check("two_node_moments", two_node_ok)
+    check("couette", couette_ok)
     check("pressure_vs_bgk", pressure_ok)
     check("channel_closed_form", channel_ok)
     check("poiseuille_eq12", poiseuille_ok)

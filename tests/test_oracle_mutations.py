@@ -43,6 +43,10 @@ MUTANTS = {
                      "L->opp[i] = (i % 2 == 1) ? i : i - 1;"),
     "velocity_component_swap": ("uy[src] + G->gh[1], uz[src] + G->gh[2]);",
                                 "uz[src] + G->gh[1], uy[src] + G->gh[2]);"),
+    # the O(u^2) part of Eq. (3): twice the coefficients, or none at all
+    "quadratic_doubled": ("(4.5 * cu) * cu) - 1.5 * vv;", "(9.0 * cu) * cu) - 3.0 * vv;"),
+    "quadratic_dropped": ("(3.0 * cu + (4.5 * cu) * cu) - 1.5 * vv;", "(3.0 * cu);"),
+    "quadratic_velocity_term_only": ("- 1.5 * vv;", "- 0.5 * vv;"),
 }
 
 
@@ -115,8 +119,13 @@ def _quick_pins():
         got = np.concatenate([out.drho[None], out.u])
         return np.abs(got - pred).max() <= 1e-6 * np.abs(pred).max()
 
+    def two_node_ok():
+        from test_oracle_pins import two_node_moments_error
+        return all(two_node_moments_error(q, a) <= 1e-16 for q in (15, 19, 27) for a in range(3))
+
     check("lattice", lattice_ok)
     check("bgk_bitwise", bgk_ok)
+    check("two_node_moments", two_node_ok)
     check("channel_closed_form", channel_ok)
     check("uniform_flow", uniform_ok)
     check("linear_modes", linear_ok)
@@ -140,4 +149,5 @@ def test_planted_mistake_is_caught(name, tmp_path):
                    check=True, capture_output=True)
     with oracle.use_library(str(so)):
         failed = _quick_pins()
+    print(f"[mutant] {name}: caught by {failed}")
     assert failed, f"mutant {name} passed every pin"

@@ -297,6 +297,59 @@ def test_linear_fourier_mode(q):
 
 
 # --------------------------------------------------------------------------
+# P9: second and third moments of the equilibrium (Eq. (3), Section 2).  On
+# a periodic lattice of two nodes along axis a (one node across the other
+# axes), node 0 receives its c_a = 0 directions from itself and its
+# c_a = +-1 directions from node 1, and node 1 the other way round.  The
+# equilibrium of Eq. (3) has the momentum-flux tensor sum_k c c f_k^eq =
+# rho/3 I + rho v v and the third moment sum_k c_a^2 c_b f_k^eq = rho v_b / 3
+# (b != a, from fourth-order isotropy), and the c_a != 0 weights add up to
+# 1/3.  With v = 0 at node 0 and g = 0, one step therefore gives exactly
+#   drho'(0) = (2/3) drho_0 + (1/3) drho_1 + rho_1 v_a^2,
+#   drho'(1) = (2/3) drho_1 + (1/3) drho_0 - rho_1 v_a^2,
+#   j'(0) = rho_1 (v_a along a, v_b / 3 across),
+#   j'(1) = rho_1 (0 along a, 2 v_b / 3 across).
+# A rescaled or dropped O(u^2) term moves rho_1 v_a^2; a wrong linear term
+# or weight moves j'.  These flows cancel nothing quadratic, unlike the
+# channel, shear-wave, uniform-flow and linear-mode pins.
+# --------------------------------------------------------------------------
+def two_node_moments_error(q: int, axis: int) -> float:
+    """Largest deviation of one oracle step from the closed form above."""
+    shape = [1, 1, 1]                       # (nz, ny, nx)
+    shape[2 - axis] = 2
+    d0, d1 = 3.0e-3, -2.0e-3
+    v1 = np.array([0.031, -0.017, 0.023])
+    drho = np.zeros(shape)
+    u = np.zeros((3,) + tuple(shape))
+    idx0 = (0, 0, 0)
+    idx1 = tuple(1 if i == 2 - axis else 0 for i in range(3))
+    drho[idx0], drho[idx1] = d0, d1
+    for b in range(3):
+        u[(b,) + idx1] = v1[b]
+    st = oracle.State(np.zeros(shape, np.uint8), drho, u)
+    out = oracle.run(q, st, [0.0, 0.0, 0.0], 1)
+    rho1 = 1.0 + d1
+    va2 = v1[axis] ** 2
+    want_d0 = (2.0 / 3.0) * d0 + d1 / 3.0 + rho1 * va2
+    want_d1 = (2.0 / 3.0) * d1 + d0 / 3.0 - rho1 * va2
+    across = np.arange(3) != axis
+    want_j0 = rho1 * np.where(across, v1 / 3.0, v1)
+    want_j1 = rho1 * np.where(across, 2.0 * v1 / 3.0, 0.0)
+    err = max(abs(out.drho[idx0] - want_d0), abs(out.drho[idx1] - want_d1))
+    for idx, want in ((idx0, want_j0), (idx1, want_j1)):
+        j = np.array([out.u[(b,) + idx] for b in range(3)]) * (1.0 + out.drho[idx])
+        err = max(err, np.abs(j - want).max())
+    return float(err)
+
+
+@pytest.mark.parametrize("q", LATTICES)
+@pytest.mark.parametrize("axis", (0, 1, 2))
+def test_two_node_second_and_third_moments(q, axis):
+    # terms are O(1e-3); FP64 rounding of one step is O(1e-18)
+    assert two_node_moments_error(q, axis) <= 1e-16
+
+
+# --------------------------------------------------------------------------
 # Consistency of the two oracle forms (rho vs drho storage).
 # --------------------------------------------------------------------------
 @pytest.mark.parametrize("q", LATTICES)
