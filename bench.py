@@ -33,8 +33,8 @@ Sections (``--sections``, default all):
              1 % over 10000 steps.
   porosity   D3Q19 FP32 on 256^3 sphere packings (r = 8, target porosity 0.05,
              0.1, 0.2, 0.3, 0.5, 0.6, 0.7, 0.8, 0.9, seeds 2000+i), 1000 steps
-             each: the z-march on the packed and the dense state layouts and
-             the gather over the fluid-node list (kernel 3); permeability,
+             each: the z-march on the packed and the dense state layouts;
+             permeability,
              work items visited, and the chunk statistics of the paper's
              bandwidth model for porous media (fraction of lane chunks stored,
              mean porosity of the stored chunks, share of mixed chunks).
@@ -63,7 +63,7 @@ PEAK_HBM_GBS = 8000.0          # MI355X HBM3E, published
 G_MAIN = (1e-6, 0.0, 0.0)
 POROSITIES = (0.05, 0.1, 0.2, 0.3, 0.5, 0.6, 0.7, 0.8, 0.9)
 COUNTERS = os.path.join(ROOT, "profiles", "zmarch_d3q19_f32_512cube_phi07.counters.txt")
-KERNEL_SOURCES = ("tau1_device.hpp", "tau1_kernels.hpp", "tau1_zmarch.hpp",
+KERNEL_SOURCES = ("tau1_device.hpp", "tau1_args.hpp", "tau1_zmarch.hpp",
                   "tau1_zmarch_inst.hip")
 
 
@@ -363,8 +363,7 @@ def porosity_section(gr, geos, args, out):
     rows = []
     for phi, geo in zip(POROSITIES, geos):
         row = {"target": phi, "porosity": geo.porosity, "spheres": geo.spheres}
-        for layout, kernel, name in ((1, -1, "packed"), (0, -1, "dense"),
-                                     (0, 3, "fluid_list")):
+        for layout, kernel, name in ((1, -1, "packed"), (0, -1, "dense")):
             sim, res = gr.case([tau1.Sample(geo.solid)], 19, "f32", args.porosity_steps,
                                args.warmup, args.graph_chunk, -1,
                                label=f"porosity {phi} {name}", layout=layout, kernel=kernel)

@@ -94,7 +94,8 @@ typedef struct {
 typedef struct {
     int32_t lattice;        /* tau1_lattice                                    */
     int32_t precision;      /* tau1_precision                                  */
-    int32_t n_samples;      /* >= 1; > 1 = batched, one launch per step for all */
+    int32_t n_samples;      /* >= 1; > 1 = batched: samples with the same nx
+                               share one kernel launch per step            */
     int32_t graph_chunk;    /* steps per captured HIP graph; even; 0 = 100      */
     const tau1_sample *samples;
     double g[3];            /* body acceleration, same for every sample         */
@@ -102,21 +103,24 @@ typedef struct {
     void *workspace;        /* borrowed device memory, 256-byte aligned         */
     size_t workspace_bytes;
     int32_t kernel;         /* step kernel: -1 = automatic (tuned or default),
-                               0 = per-node gather, 1 = z-march tiles,
-                               3 = per-node gather over lists of the fluid
-                               nodes (one thread per fluid node: for media
-                               of low porosity; dense layout, 4 bytes of
-                               list per fluid node; TAU1_E_UNSUPPORTED with
-                               layout 1, on D2Q9 or for a sample of more
-                               than 2^32 nodes; never chosen automatically) */
+                               0 = per-node gather, 1 = z-march tiles        */
     int32_t tile;           /* z-march tile shape, -1 = automatic; 0-15 =
                                z-segment of 16/32/64/128 planes (tile % 4) x
                                load schedule (tile / 4: 0 just in time,
                                1 rows shared through LDS, 2 rolling prefetch,
                                3 shared rows on the packed layout); a packed
                                context takes 12-15, a dense one 0-11          */
-    int32_t f16_log2_scale_rho; /* F16 storage: stored = value * 2^s; 0 = 20   */
-    int32_t f16_log2_scale_u;   /* F16 storage scale of the velocity; 0 = 20   */
+    int32_t f16_log2_scale_rho; /* F16 storage: stored = value * 2^s; 0 = 16.
+                                   Half holds |value| < 65504 * 2^-s (0.9995
+                                   at s = 16) and is normal down to 2^-(14+s)
+                                   (9.3e-10 at s = 16); tau1_create rejects an
+                                   initial |rho - 1| above half that range
+                                   (TAU1_E_INVALID), and a state that grows
+                                   past it later reads back as Inf
+                                   (TAU1_E_NONFINITE from tau1_moments and
+                                   tau1_permeability)                       */
+    int32_t f16_log2_scale_u;   /* F16 scale of the stored velocity u + g/2,
+                                   0 = 16; same range and check as above    */
     const char *tune_cache; /* path of the autotune JSON cache, or NULL         */
     int32_t layout;         /* state layout: -1 = automatic (packed for F32
                                z-march contexts unless tile is 0-11, dense
@@ -138,7 +142,7 @@ typedef struct {
 typedef struct {
     int32_t lattice, precision, n_samples;
     int32_t kernel;          /* step kernel in use: 0 per-node gather,
-                                1 z-march tiles, 2 D2Q9, 3 fluid-list gather */
+                                1 z-march tiles, 2 D2Q9                     */
     int32_t tile;            /* tile shape index in use (z-march)           */
     int32_t graph_chunk;
     int32_t layout;          /* 1 if any sample is stored packed, else 0    */
@@ -153,41 +157,74 @@ typedef struct {
                                 gather kernel                               */
 } tau1_info;
 
-/* Bytes of device workspace the descriptor needs.  Host only, no GPU call. */
+/* Bytes of device workspace the descriptor needs: two copies of the state
+ * (the "AB" layout of the Tau1 algorithm, Section 2.1; d + 1 values per node,
+ * complexity table of Section 2.1.3) plus the geometry tables.  Host only, no
+ * GPU call.  *bytes is written only on TAU1_OK. */
 tau1_status tau1_workspace_size(const tau1_desc *desc, size_t *bytes);
 
-/* Validates the descriptor, encodes the geometry (bit mask, tile classes) and
- * uploads the initial state into the workspace.  Synchronous on the stream. */
+/* Validates the descriptor, encodes the geometry (the node types of Section
+ * 2.1.3: a bit mask, the wall-node lists for bounce-back, the packed chunk
+ * table) and uploads the initial rho - 1 and u into the workspace (both
+ * copies).  Host arrays are read during the call only.  Synchronous on the
+ * stream.  TAU1_E_INVALID for a bad descriptor or initial field (non-finite,
+ * rho <= 0, or outside the F16 range), TAU1_E_WORKSPACE for a missing,
+ * misaligned or too small workspace, TAU1_E_UNSUPPORTED for a valid request
+ * this build does not serve.  On error *out is NULL and nothing is owned. */
 tau1_status tau1_create(const tau1_desc *desc, tau1_ctx **out);
 
-/* Enqueues nsteps >= 0 time steps on the stream (graph replays of graph_chunk
- * steps plus single launches); does not wait. */
+/* Enqueues nsteps >= 0 time steps on the stream and returns without waiting
+ * (graph replays of graph_chunk steps, then single launches).  One step
+ * advances every fluid node of every sample by the Tau1 update: the
+ * equilibria of Eq. (3) at the sources x - c_k arrive at x (Eq. (8)), their
+ * zeroth and first moments are the new density and momentum (Eqs. (9)-(10),
+ * Section 2.1), the velocity is the momentum times one reciprocal of the
+ * density (Section 3, division-saving algorithm), and a link whose source is
+ * solid returns the node's own previous equilibrium in the opposite direction
+ * (halfway bounce-back, Eq. (11), Section 2.1.1).  Device errors surface at
+ * the next synchronising call. */
 tau1_status tau1_step(tau1_ctx *ctx, int64_t nsteps);
 
 /* Waits for the stream and reports any pending device error. */
 tau1_status tau1_sync(tau1_ctx *ctx);
 
-/* Copies the current state of one sample to host FP64 arrays: drho (N values
- * of rho - 1) and u (3N values, SoA).  Solid nodes read rho = 1, u = 0.
- * Either pointer may be NULL.  Synchronous.  TAU1_E_NONFINITE if any fluid
- * value is NaN or Inf (the arrays are still written). */
-tau1_status tau1_moments(tau1_ctx *ctx, int32_t sample, double *drho,
-                         double *u);
+/* Copies the current state of one sample to host FP64 arrays: rho (N values,
+ * the physical density of Eq. (9), rho = 1 + (rho - 1) formed in FP64) and
+ * u (3N values, SoA, the velocity of Eq. (10) divided by rho, including the
+ * g/2 shift of the forcing).  Solid nodes read rho = 1, u = 0.  Either
+ * pointer may be NULL.  Synchronous.  TAU1_E_NONFINITE if any fluid value is
+ * NaN or Inf (the arrays are still written); TAU1_E_INVALID for a sample out
+ * of range. */
+tau1_status tau1_moments(tau1_ctx *ctx, int32_t sample, double *rho, double *u);
+
+/* As tau1_moments, but the first array receives rho - 1 exactly as the state
+ * holds it (the library stores the density as rho - 1, which keeps the
+ * small density variations of Eq. (9) at full precision; solid nodes read 0).
+ * Restarting from a saved state passes this array as drho0. */
+tau1_status tau1_moments_drho(tau1_ctx *ctx, int32_t sample, double *drho,
+                              double *u);
 
 /* FP64 reductions over one sample, in a fixed order (deterministic):
- *   mass = sum over fluid nodes of rho;
+ *   mass = sum over fluid nodes of rho (Eq. (5); conserved by the update);
  *   k    = nu <u_axis> / g_axis, nu = 1/6, <.> the mean over all N nodes
  *          (Darcy permeability in lattice units; solid nodes count as 0).
- * k may be NULL; if it is not, g[axis] must be nonzero.  Synchronous. */
+ * The paper defines no permeability: this is Darcy's law with the kinematic
+ * viscosity of tau = 1, nu = (tau - 1/2)/3 = 1/6.  k may be NULL; if it is
+ * not, g[axis] must be nonzero (TAU1_E_INVALID).  Synchronous.
+ * TAU1_E_NONFINITE if a fluid node holds NaN or Inf (outputs untouched). */
 tau1_status tau1_permeability(tau1_ctx *ctx, int32_t sample,
                               int32_t axis, double *k, double *mass);
 
 /* Times each eligible step-kernel shape for trial_steps steps (state is not
  * advanced: trials write only the spare buffer), keeps the fastest and, if
- * the descriptor named a cache file, records it there.  Synchronous.  A
- * context created with kernel 3 keeps it (no shapes to choose from). */
+ * the descriptor named a cache file, records it there.  Synchronous.  An
+ * engineering aid of this library (the paper tunes thread counts by hand,
+ * Section 4). */
 tau1_status tau1_autotune(tau1_ctx *ctx, int32_t trial_steps);
 
+/* Static facts about the context (host copy); bytes_per_step is the
+ * complexity table's 2 (d+1) s bytes per fluid node plus one mask bit per
+ * node (Section 2.1.3). */
 tau1_status tau1_get_info(const tau1_ctx *ctx, tau1_info *info);
 
 /* Releases host resources (graphs, metadata); NULL-safe. */
@@ -196,9 +233,10 @@ void tau1_destroy(tau1_ctx *ctx);
 const char *tau1_strerror(tau1_status status);
 
 /* Copy-bandwidth probe (calibrates the achievable HBM rate, the GPU analogue
- * of the paper's copy loop): copies bytes/2 from the first half of buf to the
- * second half, reps times, on the stream; returns the mean seconds per copy
- * measured with HIP events.  buf is device memory of at least `bytes`. */
+ * of the copy loop the paper measures against in Section 4.2): copies
+ * bytes/2 from the first half of buf to the second half, reps times, on the
+ * stream; returns the mean seconds per copy measured with HIP events.  buf is
+ * device memory of at least `bytes`, borrowed for the call. */
 tau1_status tau1_copy_probe(void *hip_stream, void *buf, size_t bytes,
                             int32_t reps, double *seconds);
 

@@ -15,7 +15,6 @@
 #include "../../include/tau1.h"
 #include "tau1_device.hpp"
 #include "tau1_kernels.hpp"
-#include "tau1_list.hpp"
 #include "tau1_zmarch.hpp"
 #include "tau1_service.hpp"
 
@@ -32,7 +31,6 @@ size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 struct SampleHost {
     SampleDev dev;
     int64_t n_fluid;
-    int64_t list_nf = 0;         // fluid-list kernel: fluid nodes listed
     std::vector<uint32_t> ctab;  // packed layout: chunk table (4 words per entry)
     std::vector<uint8_t> rowfluid;  // z-march samples: 1 if row y + ny z holds a fluid node
 };
@@ -44,9 +42,6 @@ struct Plan {
     size_t tiles_off = 0;     // z-march work list
     size_t stage_off = 0;     // upload / readback staging
     size_t stage_bytes = 0;
-    size_t list_dev_off = 0;  // fluid-list kernel: ListDev[nsamples]
-    std::vector<ListDev> lists;  // fluid-list kernel: per-sample lists
-    int64_t list_blocks = 0;     // blocks of one fluid-list launch
     size_t total = 0;
     int64_t ntiles = 0;
     int64_t total_blocks = 0;
@@ -55,8 +50,13 @@ struct Plan {
     std::vector<SampleHost> s;
 };
 
-// Step kernel 3: the per-node gather over lists of the fluid nodes.
-constexpr int kListKernel = 3;
+// FP16 storage: stored = value * 2^s with s = 16 unless the descriptor sets
+// it.  Half's largest finite value is 65504, so a state value must stay below
+// 65504 * 2^-s; an initial field is accepted up to half of that, leaving the
+// flow room to grow.
+constexpr int kF16DefaultLog2Scale = 16;
+int f16_log2_scale(int requested) { return requested ? requested : kF16DefaultLog2Scale; }
+double f16_limit(int log2_scale) { return 0.5 * 65504.0 * std::ldexp(1.0, -log2_scale); }
 
 bool valid_lattice(int q) { return q == 9 || q == 15 || q == 19 || q == 27; }
 bool valid_precision(int p) { return p >= kF64 && p <= kBF16; }
@@ -66,9 +66,7 @@ tau1_status validate(const tau1_desc* d) {
     if (!valid_lattice(d->lattice) || !valid_precision(d->precision)) return TAU1_E_INVALID;
     if (d->n_samples < 1 || d->n_samples > kMaxSamples || !d->samples) return TAU1_E_INVALID;
     if (d->graph_chunk < 0 || (d->graph_chunk % 2) != 0) return TAU1_E_INVALID;
-    if (d->kernel < -1 || d->kernel > 1) {
-        if (d->kernel != kListKernel) return TAU1_E_INVALID;
-    }
+    if (d->kernel < -1 || d->kernel > 1) return TAU1_E_INVALID;
     if (d->tile < -1 || d->tile >= kNumTiles) return TAU1_E_INVALID;
     if (d->layout < -1 || d->layout > 1) return TAU1_E_INVALID;
     if (d->x_boundary < 0 || d->x_boundary > 1) return TAU1_E_INVALID;
@@ -100,14 +98,6 @@ tau1_status validate(const tau1_desc* d) {
 // one kernel, in FP64 and FP32; its boundaries exist only there.
 tau1_status unsupported(const tau1_desc* d) {
     if (d->lattice == 9 && (d->precision > kF32 || d->kernel != -1)) return TAU1_E_UNSUPPORTED;
-    if (d->kernel == kListKernel) {
-        // dense layout only; node indices are 32-bit
-        if (d->layout == 1) return TAU1_E_UNSUPPORTED;
-        for (int i = 0; i < d->n_samples; ++i) {
-            const tau1_sample& s = d->samples[i];
-            if (s.nx * s.ny * s.nz > (int64_t(1) << 32)) return TAU1_E_UNSUPPORTED;
-        }
-    }
     if (d->lattice != 9 && (d->x_boundary != 0 || d->wall_u[0] != 0.0 || d->wall_u[1] != 0.0 ||
                             d->wall_u[2] != 0.0))
         return TAU1_E_UNSUPPORTED;
@@ -239,26 +229,6 @@ Plan make_plan(const tau1_desc* d, bool tables) {
             off = align_up(off + (size_t)4 * sd.stride * sz, kAlign);
         }
     }
-    if (d->kernel == kListKernel) {
-        // fluid-node lists (uint32 node indices) and their descriptors
-        p.list_dev_off = off;
-        off = align_up(off + sizeof(ListDev) * d->n_samples, kAlign);
-        p.lists.resize(d->n_samples);
-        int64_t fb = 0;
-        for (int i = 0; i < d->n_samples; ++i) {
-            const tau1_sample& in = d->samples[i];
-            const int64_t n = in.nx * in.ny * in.nz;
-            int64_t nf = 0;
-            for (int64_t j = 0; j < n; ++j) nf += in.solid[j] ? 0 : 1;
-            p.s[i].list_nf = nf;
-            p.lists[i].list = (int64_t)off;
-            p.lists[i].nf = nf;
-            p.lists[i].fblock0 = fb;
-            fb += (nf + kGatherBlock - 1) / kGatherBlock;
-            off = align_up(off + sizeof(uint32_t) * (size_t)std::max<int64_t>(nf, 1), kAlign);
-        }
-        p.list_blocks = fb;
-    }
     const int64_t stage_nodes = std::min<int64_t>(maxn, kStageNodes);
     p.stage_off = off;
     // solid byte + drho + 3 u (FP64) on upload; 4 FP64 on readback
@@ -292,9 +262,6 @@ struct tau1_ctx {
         StepArgs args[2];
     };
     std::vector<ZGroup> zgroups;
-    // fluid-list kernel: device address of the ListDev array (its second
-    // argument; the other kernels take one argument and ignore it)
-    const ListDev* list_dev = nullptr;
     int parity = 0;
     int64_t steps_done = 0;
     int64_t n_nodes = 0, n_fluid = 0;
@@ -321,27 +288,6 @@ tau1_status fail_hip(tau1_ctx* ctx, hipError_t e) {
 // --- kernel dispatch -------------------------------------------------------
 template <int Q, int P>
 void* gather_fn() { return reinterpret_cast<void*>(&k_gather<Q, P>); }
-
-template <int Q, int P>
-void* gather_list_fn() { return reinterpret_cast<void*>(&k_gather_list<Q, P>); }
-
-void* pick_gather_list(int q, int p) {
-    switch (q * 10 + p) {
-        case 150: return gather_list_fn<15, kF64>();
-        case 151: return gather_list_fn<15, kF32>();
-        case 152: return gather_list_fn<15, kF16>();
-        case 153: return gather_list_fn<15, kBF16>();
-        case 190: return gather_list_fn<19, kF64>();
-        case 191: return gather_list_fn<19, kF32>();
-        case 192: return gather_list_fn<19, kF16>();
-        case 193: return gather_list_fn<19, kBF16>();
-        case 270: return gather_list_fn<27, kF64>();
-        case 271: return gather_list_fn<27, kF32>();
-        case 272: return gather_list_fn<27, kF16>();
-        case 273: return gather_list_fn<27, kBF16>();
-    }
-    return nullptr;
-}
 
 void* pick_gather(int q, int p) {
     switch (q * 10 + p) {
@@ -382,8 +328,7 @@ void* pick_d2q9(int p) {
 }
 
 // Launch geometry of one step kernel: z-march group g (kernel 1), the
-// per-node gather over every sample (kernel 0), the D2Q9 kernel (2) or the
-// gather over the fluid-node lists (3).
+// per-node gather over every sample (kernel 0) or the D2Q9 kernel (2).
 Launch step_launch(const tau1_ctx* ctx, int kernel, int tile, int g) {
     Launch l{};
     if (kernel == 1) {
@@ -393,11 +338,6 @@ Launch step_launch(const tau1_ctx* ctx, int kernel, int tile, int g) {
         l.fn = pick_zmarch(ctx->lattice, ctx->precision, grp.variant, mode);
         l.block = dim3(zmarch_threads(tile));
         l.grid = dim3((unsigned)zmarch_grid(grp.args[0].ntiles, tile));
-        l.shmem = 0;
-    } else if (kernel == kListKernel) {
-        l.fn = pick_gather_list(ctx->lattice, ctx->precision);
-        l.block = dim3(kGatherBlock);
-        l.grid = dim3((unsigned)ctx->plan.list_blocks);
         l.shmem = 0;
     } else {
         l.fn = kernel == 2 ? pick_d2q9(ctx->precision) : pick_gather(ctx->lattice, ctx->precision);
@@ -422,7 +362,7 @@ tau1_status launch_one(tau1_ctx* ctx, int kernel, int tile, int parity) {
         const Launch l = step_launch(ctx, kernel, tile, g);
         if (!l.fn) return TAU1_E_UNSUPPORTED;
         if (l.grid.x == 0) continue;
-        void* params[] = {launch_args(ctx, kernel, g, parity), &ctx->list_dev};
+        void* params[] = {launch_args(ctx, kernel, g, parity)};
         HIP_TRY(hipLaunchKernel(l.fn, l.grid, l.block, params, l.shmem, ctx->stream));
     }
     return TAU1_OK;
@@ -451,8 +391,7 @@ tau1_status build_graph(tau1_ctx* ctx) {
         if (l.grid.x == 0) continue;
         hipGraphNode_t prev = nullptr;
         for (int s = 0; s < ctx->graph_chunk; ++s) {
-            void* params[] = {launch_args(ctx, ctx->kernel, g, (ctx->parity + s) & 1),
-                              &ctx->list_dev};
+            void* params[] = {launch_args(ctx, ctx->kernel, g, (ctx->parity + s) & 1)};
             hipKernelNodeParams kp{};
             kp.func = l.fn;
             kp.gridDim = l.grid;
@@ -606,7 +545,8 @@ tau1_status upload_sample(tau1_ctx* ctx, int s, const tau1_sample& in) {
 }
 
 template <int P>
-tau1_status export_sample_t(tau1_ctx* ctx, int s, double* drho, double* u, int* nbad) {
+tau1_status export_sample_t(tau1_ctx* ctx, int s, double* drho, double* u, int* nbad,
+                            bool phys_rho) {
     const SampleDev& sd = ctx->plan.s[s].dev;
     uint8_t* stage = ctx->base + ctx->plan.stage_off;
     int* bad = reinterpret_cast<int*>(ctx->base + ctx->plan.partial_off +
@@ -618,7 +558,8 @@ tau1_status export_sample_t(tau1_ctx* ctx, int s, double* drho, double* u, int* 
     for (int64_t i0 = 0; i0 < n; i0 += chunk) {
         const int64_t len = std::min(chunk, n - i0);
         hipLaunchKernelGGL(k_export<P>, dim3((unsigned)((len + 255) / 256)), dim3(256), 0,
-                           ctx->stream, ctx->args[ctx->parity], s, out, i0, len, bad);
+                           ctx->stream, ctx->args[ctx->parity], s, out, i0, len, bad,
+                           phys_rho ? 1 : 0);
         HIP_TRY(hipGetLastError());
         if (drho)
             HIP_TRY(hipMemcpyAsync(drho + i0, out, sizeof(double) * len, hipMemcpyDeviceToHost,
@@ -706,48 +647,6 @@ tau1_status check_usable(const tau1_ctx* ctx) {
 // ===========================================================================
 // C ABI
 // ===========================================================================
-namespace {
-
-// Fluid-node lists of the fluid-list kernel: node indices in increasing
-// order, built on the host and copied in pieces, then the per-sample
-// descriptors.
-tau1_status upload_lists(tau1_ctx* ctx, const tau1_desc* d) {
-    std::vector<uint32_t> buf;
-    try {
-        buf.resize((size_t)kStageNodes);
-    } catch (const std::bad_alloc&) {
-        return TAU1_E_NOMEM;
-    }
-    const int64_t piece = (int64_t)buf.size();
-    for (int i = 0; i < d->n_samples; ++i) {
-        const tau1_sample& in = d->samples[i];
-        const int64_t n = in.nx * in.ny * in.nz;
-        const ListDev& l = ctx->plan.lists[i];
-        int64_t written = 0, fill = 0;
-        for (int64_t j = 0; j <= n; ++j) {
-            if (j < n && !in.solid[j]) buf[(size_t)fill++] = (uint32_t)j;
-            if (fill == piece || (j == n && fill > 0)) {
-                if (written + fill > l.nf) return TAU1_E_INVALID;  // solid changed under us
-                HIP_TRY(hipMemcpyAsync(ctx->base + l.list + sizeof(uint32_t) * written,
-                                       buf.data(), sizeof(uint32_t) * (size_t)fill,
-                                       hipMemcpyHostToDevice, ctx->stream));
-                HIP_TRY(hipStreamSynchronize(ctx->stream));  // buf is refilled next
-                written += fill;
-                fill = 0;
-            }
-        }
-        if (written != l.nf) return TAU1_E_INVALID;
-    }
-    HIP_TRY(hipMemcpyAsync(ctx->base + ctx->plan.list_dev_off, ctx->plan.lists.data(),
-                           sizeof(ListDev) * ctx->plan.lists.size(), hipMemcpyHostToDevice,
-                           ctx->stream));
-    HIP_TRY(hipStreamSynchronize(ctx->stream));
-    ctx->list_dev = reinterpret_cast<const ListDev*>(ctx->base + ctx->plan.list_dev_off);
-    return TAU1_OK;
-}
-
-}  // namespace
-
 extern "C" {
 
 const char* tau1_strerror(tau1_status s) {
@@ -784,16 +683,31 @@ tau1_status tau1_create(const tau1_desc* desc, tau1_ctx** out) {
     tau1_status v = validate(desc);
     if (v == TAU1_OK) v = unsupported(desc);
     if (v != TAU1_OK) return v;
-    // non-finite initial fields are rejected before any GPU work
+    // non-finite initial fields, and for FP16 storage fields beyond its range
+    // at the chosen scales, are rejected before any GPU work
+    const bool f16 = desc->precision == kF16;
+    const double lim_r = f16_limit(f16_log2_scale(desc->f16_log2_scale_rho));
+    const double lim_u = f16_limit(f16_log2_scale(desc->f16_log2_scale_u));
     for (int i = 0; i < desc->n_samples; ++i) {
         const tau1_sample& s = desc->samples[i];
         const int64_t n = s.nx * s.ny * s.nz;
         if (s.drho0)
-            for (int64_t j = 0; j < n; ++j)
+            for (int64_t j = 0; j < n; ++j) {
                 if (!std::isfinite(s.drho0[j]) || s.drho0[j] <= -1.0) return TAU1_E_INVALID;
+                if (f16 && !s.solid[j] && std::fabs(s.drho0[j]) >= lim_r) return TAU1_E_INVALID;
+            }
         if (s.u0)
             for (int64_t j = 0; j < 3 * n; ++j)
                 if (!std::isfinite(s.u0[j])) return TAU1_E_INVALID;
+        if (f16)
+            for (int a = 0; a < 3; ++a) {
+                const double gh = 0.5 * desc->g[a];
+                if (std::fabs(gh) >= lim_u) return TAU1_E_INVALID;
+                if (!s.u0) continue;
+                for (int64_t j = 0; j < n; ++j)
+                    if (!s.solid[j] && std::fabs(s.u0[(int64_t)a * n + j] + gh) >= lim_u)
+                        return TAU1_E_INVALID;
+            }
     }
     if (!desc->workspace) return TAU1_E_WORKSPACE;
     if (reinterpret_cast<uintptr_t>(desc->workspace) % kAlign != 0) return TAU1_E_WORKSPACE;
@@ -830,8 +744,8 @@ tau1_status tau1_create(const tau1_desc* desc, tau1_ctx** out) {
     ctx->cache = desc->tune_cache ? desc->tune_cache : "";
     for (int a = 0; a < 3; ++a) ctx->g[a] = desc->g[a];
 
-    const int lsr = desc->f16_log2_scale_rho ? desc->f16_log2_scale_rho : 20;
-    const int lsu = desc->f16_log2_scale_u ? desc->f16_log2_scale_u : 20;
+    const int lsr = f16_log2_scale(desc->f16_log2_scale_rho);
+    const int lsu = f16_log2_scale(desc->f16_log2_scale_u);
     for (int p = 0; p < 2; ++p) {
         StepArgs& a = ctx->args[p];
         std::memset(&a, 0, sizeof a);
@@ -893,7 +807,6 @@ tau1_status tau1_create(const tau1_desc* desc, tau1_ctx** out) {
     }
     for (int i = 0; st == TAU1_OK && i < ctx->nsamples; ++i)
         st = upload_sample(ctx, i, desc->samples[i]);
-    if (st == TAU1_OK && desc->kernel == kListKernel) st = upload_lists(ctx, desc);
     if (st != TAU1_OK) {
         delete ctx;
         return st;
@@ -959,19 +872,35 @@ tau1_status tau1_sync(tau1_ctx* ctx) {
     return TAU1_OK;
 }
 
-tau1_status tau1_moments(tau1_ctx* ctx, int32_t sample, double* drho, double* u) {
+}  // extern "C"
+
+namespace {
+
+tau1_status moments_impl(tau1_ctx* ctx, int32_t sample, double* r, double* u, bool phys_rho) {
     tau1_status st = check_usable(ctx);
     if (st != TAU1_OK) return st;
     if (sample < 0 || sample >= ctx->nsamples) return TAU1_E_INVALID;
     int nbad = 0;
     switch (ctx->precision) {
-        case kF64: st = export_sample_t<kF64>(ctx, sample, drho, u, &nbad); break;
-        case kF32: st = export_sample_t<kF32>(ctx, sample, drho, u, &nbad); break;
-        case kF16: st = export_sample_t<kF16>(ctx, sample, drho, u, &nbad); break;
-        case kBF16: st = export_sample_t<kBF16>(ctx, sample, drho, u, &nbad); break;
+        case kF64: st = export_sample_t<kF64>(ctx, sample, r, u, &nbad, phys_rho); break;
+        case kF32: st = export_sample_t<kF32>(ctx, sample, r, u, &nbad, phys_rho); break;
+        case kF16: st = export_sample_t<kF16>(ctx, sample, r, u, &nbad, phys_rho); break;
+        case kBF16: st = export_sample_t<kBF16>(ctx, sample, r, u, &nbad, phys_rho); break;
     }
     if (st != TAU1_OK) return st;
     return nbad ? TAU1_E_NONFINITE : TAU1_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+tau1_status tau1_moments(tau1_ctx* ctx, int32_t sample, double* rho, double* u) {
+    return moments_impl(ctx, sample, rho, u, true);
+}
+
+tau1_status tau1_moments_drho(tau1_ctx* ctx, int32_t sample, double* drho, double* u) {
+    return moments_impl(ctx, sample, drho, u, false);
 }
 
 tau1_status tau1_permeability(tau1_ctx* ctx, int32_t sample, int32_t axis, double* k,
@@ -999,7 +928,6 @@ tau1_status tau1_autotune(tau1_ctx* ctx, int32_t trial_steps) {
     tau1_status st = check_usable(ctx);
     if (st != TAU1_OK) return st;
     if (trial_steps < 1) return TAU1_E_INVALID;
-    if (ctx->kernel == kListKernel) return TAU1_OK;  // no shapes to choose from
     if (!zmarch_eligible(ctx)) return TAU1_OK;  // only the gather kernel applies
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0));

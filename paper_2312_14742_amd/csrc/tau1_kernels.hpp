@@ -2,51 +2,9 @@
 // (geometry encode, state upload/readback, FP64 reductions, copy probe).
 #pragma once
 
-#include "tau1_device.hpp"
+#include "tau1_args.hpp"
 
 namespace tau1 {
-
-// Arguments shared by every step kernel (passed by value; one copy per
-// ping-pong parity is kept by the host so HIP graph nodes can point at it).
-struct StepArgs {
-    uint8_t* base;              // workspace base
-    const SampleDev* samples;   // device array, nsamples entries
-    const int32_t* tiles;       // z-march work list (sample, ty, tz) triples
-    int32_t nsamples;
-    int32_t parity;             // buffer read this step; the other is written
-    int32_t ntiles;             // z-march work items
-    int32_t pad;
-    double gh[3];               // g / 2 (FP64)
-    float ghf[3];               // g / 2 (FP32)
-    float scale_rho, inv_scale_rho, scale_u, inv_scale_u;  // F16 storage
-    // D2Q9 boundaries: Zou-He pressure columns at x = 0 and nx - 1 (xbc = 1)
-    // with densities 1 + din, 1 + dout; velocity of the moving walls
-    int32_t xbc;
-    int32_t pad2;
-    double din, dout;
-    double uw[2];
-};
-
-template <int P>
-__device__ __forceinline__ typename Storage<P>::T inv_scale_rho(const StepArgs& a) {
-    if constexpr (P == kF16) return a.inv_scale_rho; else return 1;
-}
-template <int P>
-__device__ __forceinline__ typename Storage<P>::T inv_scale_u(const StepArgs& a) {
-    if constexpr (P == kF16) return a.inv_scale_u; else return 1;
-}
-template <int P>
-__device__ __forceinline__ typename Storage<P>::T scale_rho(const StepArgs& a) {
-    if constexpr (P == kF16) return a.scale_rho; else return 1;
-}
-template <int P>
-__device__ __forceinline__ typename Storage<P>::T scale_u(const StepArgs& a) {
-    if constexpr (P == kF16) return a.scale_u; else return 1;
-}
-template <typename T>
-__device__ __forceinline__ T gh_of(const StepArgs& a, int d) {
-    if constexpr (sizeof(T) == 8) return a.gh[d]; else return a.ghf[d];
-}
 
 // Sample owning a block of a per-node launch (samples sorted by block0).
 __device__ __forceinline__ int sample_of_block(const SampleDev* s, int n, int64_t b) {
@@ -281,10 +239,12 @@ __global__ void k_upload(StepArgs a, int s, const uint8_t* __restrict__ solid,
 
 // State readback: nodes [i0, i0 + len) of one sample, current buffer, into
 // FP64 staging (drho | ux | uy | uz, each len values); u = v - g/2 in FP64;
-// solid nodes read 0.  Counts non-finite fluid values into *bad.
+// solid nodes read 0.  With phys_rho the first array holds rho = 1 + drho
+// (formed in FP64; 1 at solid nodes) instead.  Counts non-finite fluid values
+// into *bad.
 template <int P>
 __global__ void k_export(StepArgs a, int s, double* __restrict__ out, int64_t i0,
-                         int64_t len, int* bad) {
+                         int64_t len, int* bad, int phys_rho) {
     using St = Storage<P>;
     using S = typename St::S;
     using T = typename St::T;
@@ -307,20 +267,51 @@ __global__ void k_export(StepArgs a, int s, double* __restrict__ out, int64_t i0
         if (!isfinite(d) || !isfinite(ux) || !isfinite(uy) || !isfinite(uz))
             atomicAdd(bad, 1);
     }
-    out[t] = d;
+    out[t] = phys_rho ? 1.0 + d : d;
     out[len + t] = ux;
     out[2 * len + t] = uy;
     out[3 * len + t] = uz;
 }
 
 // ---------------------------------------------------------------------------
-// FP64 reductions (a6), deterministic: block b owns the contiguous node range
-// [b*chunk, (b+1)*chunk); each thread sums its strided sub-sequence in order,
-// then the block combines in a fixed tree.  Partials: (sum drho, sum u_axis,
-// fluid count, non-finite count) per block.
+// FP64 reductions (mass and permeability), deterministic: block b owns the
+// contiguous node range [b*chunk, (b+1)*chunk); each thread sums its strided
+// sub-sequence in order, each wave combines its lanes with a fixed butterfly
+// of lane shuffles, and the block's first wave adds the four wave totals in
+// wave order.  Partials: (sum drho, sum u_axis, fluid count, non-finite
+// count) per block.  The same order on every run gives the same bits.
 // ---------------------------------------------------------------------------
 constexpr int kReduceBlocks = 1024;
 constexpr int kReduceThreads = 256;
+constexpr int kReduceWaves = kReduceThreads / 64;
+
+// Sum over the 64 lanes of a wave by an xor butterfly: lane i adds lane
+// i ^ m for m = 32, 16, ..., 1.  Both partners form the same sum (addition
+// commutes exactly), so every lane ends with the same total.
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+    return v;
+}
+
+// The four sums of a block in wave order; valid in thread 0.
+__device__ __forceinline__ void block_sum4(double (&acc)[4]) {
+    __shared__ double sh[kReduceWaves][4];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[c] = wave_sum(acc[c]);
+    if (lane == 0)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) sh[wave][c] = acc[c];
+    __syncthreads();
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            double t = sh[0][c];
+            for (int w = 1; w < kReduceWaves; ++w) t += sh[w][c];
+            acc[c] = t;
+        }
+}
 
 template <int P>
 __global__ __launch_bounds__(kReduceThreads) void k_reduce_partial(StepArgs a, int s, int axis,
@@ -334,7 +325,7 @@ __global__ __launch_bounds__(kReduceThreads) void k_reduce_partial(StepArgs a, i
     const uint32_t* mask = reinterpret_cast<const uint32_t*>(a.base + sd.mask);
     const S* p = reinterpret_cast<const S*>(a.base + sd.state[a.parity]);
     const S* pu = p + (int64_t)(1 + axis) * sd.stride;
-    double sdr = 0, su = 0, nf = 0, nb = 0;
+    double acc[4] = {0, 0, 0, 0};  // sum drho, sum u, fluid nodes, non-finite nodes
     for (int64_t i = beg + threadIdx.x; i < end; i += kReduceThreads) {
         const int x = (int)(i % sd.nx);
         const int y = (int)((i / sd.nx) % sd.ny);
@@ -343,23 +334,15 @@ __global__ __launch_bounds__(kReduceThreads) void k_reduce_partial(StepArgs a, i
         const int64_t e = state_slot(a.base, sd, x, y, z, i);
         const double d = (double)St::load(p, e, inv_scale_rho<P>(a));
         const double u = (double)St::load(pu, e, inv_scale_u<P>(a)) - a.gh[axis];
-        if (!isfinite(d) || !isfinite(u)) { nb += 1; continue; }
-        sdr += d;
-        su += u;
-        nf += 1;
+        if (!isfinite(d) || !isfinite(u)) { acc[3] += 1; continue; }
+        acc[0] += d;
+        acc[1] += u;
+        acc[2] += 1;
     }
-    __shared__ double sh[4][kReduceThreads];
-    sh[0][threadIdx.x] = sdr;
-    sh[1][threadIdx.x] = su;
-    sh[2][threadIdx.x] = nf;
-    sh[3][threadIdx.x] = nb;
-    __syncthreads();
-    for (int w = kReduceThreads / 2; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w)
-            for (int c = 0; c < 4; ++c) sh[c][threadIdx.x] += sh[c][threadIdx.x + w];
-        __syncthreads();
-    }
-    if (threadIdx.x < 4) partial[blockIdx.x * 4 + threadIdx.x] = sh[threadIdx.x][0];
+    block_sum4(acc);
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) partial[blockIdx.x * 4 + c] = acc[c];
 }
 
 }  // namespace tau1

@@ -24,29 +24,23 @@ __global__ void k_pack_mask(const uint8_t* __restrict__ solid, uint32_t* __restr
     mask[(row0 + r) * words + w] = bits;
 }
 
-// Final pass over the kReduceBlocks partials (one block, fixed tree); writes
-// out[0] = mass, out[1] = permeability (or 0 when g_axis == 0), out[2] = fluid
-// count, out[3] = non-finite count.
+// Final pass over the kReduceBlocks partials (one block; thread t adds
+// partials t, t + 256, ... in order, then the fixed wave butterfly and wave
+// order of block_sum4); writes out[0] = mass, out[1] = permeability (or 0
+// when g_axis == 0), out[2] = fluid count, out[3] = non-finite count.
 __global__ __launch_bounds__(kReduceThreads) void k_reduce_final(const double* __restrict__ partial,
                                                                  int64_t n, double g_axis,
                                                                  double* __restrict__ out) {
-    __shared__ double sh[4][kReduceThreads];
     double acc[4] = {0, 0, 0, 0};
     for (int b = threadIdx.x; b < kReduceBlocks; b += kReduceThreads)
         for (int c = 0; c < 4; ++c) acc[c] += partial[b * 4 + c];
-    for (int c = 0; c < 4; ++c) sh[c][threadIdx.x] = acc[c];
-    __syncthreads();
-    for (int w = kReduceThreads / 2; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w)
-            for (int c = 0; c < 4; ++c) sh[c][threadIdx.x] += sh[c][threadIdx.x + w];
-        __syncthreads();
-    }
+    block_sum4(acc);
     if (threadIdx.x == 0) {
-        const double sum_drho = sh[0][0], sum_u = sh[1][0], nf = sh[2][0];
+        const double sum_drho = acc[0], sum_u = acc[1], nf = acc[2];
         out[0] = nf + sum_drho;
         out[1] = g_axis != 0.0 ? (1.0 / 6.0) * (sum_u / (double)n) / g_axis : 0.0;
         out[2] = nf;
-        out[3] = sh[3][0];
+        out[3] = acc[3];
     }
 }
 

@@ -42,7 +42,7 @@
 #include <string>
 #include <vector>
 
-#include "tau1_kernels.hpp"
+#include "tau1_args.hpp"
 
 // Multiply-adds fuse only where one expression writes a * b + c (and at the
 // explicit fmaf calls), never across statements: every tile and load

@@ -28,8 +28,8 @@ TAU1_E_WORKSPACE = -6
 
 # Every function the header declares (checked against include/tau1.h by the tests).
 EXPORTS = ("tau1_workspace_size", "tau1_create", "tau1_step", "tau1_sync",
-           "tau1_moments", "tau1_permeability", "tau1_autotune", "tau1_get_info",
-           "tau1_destroy", "tau1_strerror", "tau1_copy_probe")
+           "tau1_moments", "tau1_moments_drho", "tau1_permeability", "tau1_autotune",
+           "tau1_get_info", "tau1_destroy", "tau1_strerror", "tau1_copy_probe")
 
 
 class Tau1Error(RuntimeError):
@@ -97,6 +97,8 @@ def _lib() -> ctypes.CDLL:
         lib.tau1_sync.restype = st
         lib.tau1_moments.argtypes = [P, ctypes.c_int32, P, P]
         lib.tau1_moments.restype = st
+        lib.tau1_moments_drho.argtypes = [P, ctypes.c_int32, P, P]
+        lib.tau1_moments_drho.restype = st
         lib.tau1_permeability.argtypes = [P, ctypes.c_int32, ctypes.c_int32,
                                           ctypes.POINTER(ctypes.c_double),
                                           ctypes.POINTER(ctypes.c_double)]
@@ -195,8 +197,7 @@ class Sim:
     """One Tau1 context over one or more samples (batched when several).
 
     ``precision`` is one of "f64", "f32", "f16", "bf16".  ``kernel`` -1 picks
-    automatically, 0 forces the per-node gather kernel, 1 the z-march tiles,
-    3 the per-node gather over a list of the fluid nodes (dense layout).
+    automatically, 0 forces the per-node gather kernel, 1 the z-march tiles.
     ``layout`` -1 picks the state layout automatically, 0 is dense, 1 packed
     (all-solid lane chunks not stored).  ``lattice=9`` is the D2Q9 validation
     lattice (samples of shape (1, ny, nx); solid values 0 fluid, 1 wall,
@@ -250,16 +251,25 @@ class Sim:
     def sync(self):
         _check(_lib().tau1_sync(self._c()), "tau1_sync")
 
-    def moments(self, sample: int = 0, allow_nonfinite: bool = False):
-        """(drho, u) as FP64 numpy arrays of shapes (nz, ny, nx), (3, nz, ny, nx)."""
+    def _read(self, fn, what, sample, allow_nonfinite):
         s = self.samples[sample]
         shape = s.solid.shape
-        drho = np.empty(shape, dtype=np.float64)
+        first = np.empty(shape, dtype=np.float64)
         u = np.empty((3,) + shape, dtype=np.float64)
-        st = _lib().tau1_moments(self._c(), int(sample), drho.ctypes.data, u.ctypes.data)
+        st = fn(self._c(), int(sample), first.ctypes.data, u.ctypes.data)
         if not (allow_nonfinite and st == TAU1_E_NONFINITE):
-            _check(st, "tau1_moments")
-        return drho, u
+            _check(st, what)
+        return first, u
+
+    def moments(self, sample: int = 0, allow_nonfinite: bool = False):
+        """(drho, u) with drho = rho - 1 as stored (tau1_moments_drho), FP64
+        numpy arrays of shapes (nz, ny, nx), (3, nz, ny, nx)."""
+        return self._read(_lib().tau1_moments_drho, "tau1_moments_drho", sample,
+                          allow_nonfinite)
+
+    def rho_u(self, sample: int = 0, allow_nonfinite: bool = False):
+        """(rho, u), the physical density and velocity (tau1_moments)."""
+        return self._read(_lib().tau1_moments, "tau1_moments", sample, allow_nonfinite)
 
     def permeability(self, sample: int = 0, axis: int = 0, with_k: bool = True):
         """(k, mass) from the FP64 device reduction (k is None if with_k is False)."""

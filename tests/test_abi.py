@@ -146,42 +146,56 @@ def test_null_context_calls(lib):
     lib.tau1_destroy(None)                    # NULL-safe
 
 
-def test_fluid_list_kernel_workspace():
-    """Kernel 3 adds, to the dense layout, one uint32 index per fluid node per
-    sample and one 24-byte descriptor per sample (256-byte aligned pieces)."""
-    def align(v):
-        return (v + 255) // 256 * 256
-    a = inputs.random_state(40, 6, 5, seed=77, solid_frac=0.8)[0]
-    b = inputs.random_state(64, 3, 2, seed=78, solid_frac=0.3)[0]
-    dense = tau1.workspace_size([(a,), (b,)], kernel=0)
-    listed = tau1.workspace_size([(a,), (b,)], kernel=3)
-    extra = align(24 * 2) + align(4 * int((a == 0).sum())) + align(4 * int((b == 0).sum()))
-    assert listed == dense + extra
-    # an all-solid sample still gets one (unused) slot
-    s = np.ones((2, 2, 2), np.uint8)
-    assert tau1.workspace_size([(s,)], kernel=3) == \
-        tau1.workspace_size([(s,)], kernel=0) + align(24) + align(4)
-
-
-@pytest.mark.parametrize("kw,status", [
-    (dict(kernel=3, layout=1), tau1.TAU1_E_UNSUPPORTED),   # dense layout only
-    (dict(kernel=3, lattice=9), tau1.TAU1_E_UNSUPPORTED),  # 3-D lattices only
-    (dict(kernel=2), tau1.TAU1_E_INVALID),                 # 2 is the D2Q9 kernel's own
-    (dict(kernel=4), tau1.TAU1_E_INVALID),
-])
-def test_fluid_list_kernel_requests(lib, kw, status):
+@pytest.mark.parametrize("kernel", [2, 3, 4])
+def test_unknown_kernel_rejected(lib, kernel):
+    """Kernels 0 (per-node gather) and 1 (z-march) exist on the 3-D lattices;
+    2 is the D2Q9 kernel's own number and is not requested."""
     solid = np.zeros((1, 4, 8), np.uint8)
-    d, keep = tau1._desc([tau1.Sample(solid)], kw.get("lattice", 19), "f32", (0, 0, 0), 0,
-                         kw["kernel"], -1, (0, 0), None, kw.get("layout", -1))
+    d, keep = tau1._desc([tau1.Sample(solid)], 19, "f32", (0, 0, 0), 0, kernel, -1, (0, 0),
+                         None, -1)
     n = ctypes.c_size_t(0)
-    assert lib.tau1_workspace_size(ctypes.byref(d), ctypes.byref(n)) == status
+    assert lib.tau1_workspace_size(ctypes.byref(d), ctypes.byref(n)) == tau1.TAU1_E_INVALID
 
 
-def test_fluid_list_kernel_rejects_more_than_2_32_nodes(lib):
-    """Node indices of the lists are 32-bit (checked before the mask is read;
-    a small array stands in for the large one)."""
-    d, keep = tau1._desc([tau1.Sample(np.zeros((2, 2, 2), np.uint8))], 19, "f32", (0, 0, 0), 0,
-                         3, -1, (0, 0), None, -1)
-    keep[0].nz, keep[0].ny, keep[0].nx = 3, 1 << 11, 1 << 20
-    n = ctypes.c_size_t(0)
-    assert lib.tau1_workspace_size(ctypes.byref(d), ctypes.byref(n)) == tau1.TAU1_E_UNSUPPORTED
+def _create_status(lib, solid, drho=None, u=None, precision="f16", scales=(0, 0),
+                   g=(1e-6, 0, 0)):
+    d, keep = tau1._desc([tau1.Sample(solid, drho, u)], 19, precision, g, 0, -1, -1,
+                         scales, None, -1)
+    d.workspace = None                    # the field checks come before the workspace's
+    ctx = ctypes.c_void_p(None)
+    st = lib.tau1_create(ctypes.byref(d), ctypes.byref(ctx))
+    assert not ctx.value
+    return st
+
+
+@pytest.mark.parametrize("scale,limit", [(0, 0.5 * 65504 * 2.0 ** -16),
+                                         (20, 0.5 * 65504 * 2.0 ** -20),
+                                         (12, 0.5 * 65504 * 2.0 ** -12)])
+def test_f16_range_checked_at_create(lib, scale, limit):
+    """FP16 storage keeps value * 2^s in half (largest finite 65504): an
+    initial rho - 1 or u + g/2 at or above half of 65504 * 2^-s is refused
+    before any GPU work, one just below passes the check (and only then
+    meets the missing workspace); solid nodes and the other precisions are
+    not checked."""
+    solid = np.zeros((2, 2, 4), np.uint8)
+    solid[0, 0, 0] = 1
+    for field in ("drho", "ux", "uz"):
+        for value, ok in ((0.999 * limit, True), (1.001 * limit, False), (-limit, False)):
+            drho = np.zeros(solid.shape)
+            u = np.zeros((3,) + solid.shape)
+            if field == "drho":
+                drho[1, 1, 2] = value
+            else:
+                u[0 if field == "ux" else 2, 1, 1, 2] = value - (1e-6 / 2 if field == "ux" else 0)
+            st = _create_status(lib, solid, drho, u, scales=(scale, scale))
+            assert st == (tau1.TAU1_E_WORKSPACE if ok else tau1.TAU1_E_INVALID), (field, value)
+            if not (field == "drho" and value <= -1.0):      # rho <= 0 is invalid anyway
+                assert _create_status(lib, solid, drho, u, precision="bf16") == \
+                    tau1.TAU1_E_WORKSPACE
+    # a solid node's value is not state
+    drho = np.zeros(solid.shape)
+    drho[0, 0, 0] = 10 * limit
+    assert _create_status(lib, solid, drho, scales=(scale, scale)) == tau1.TAU1_E_WORKSPACE
+    # the force shift alone can exceed the range
+    assert _create_status(lib, solid, scales=(scale, scale),
+                          g=(2.2 * limit, 0, 0)) == tau1.TAU1_E_INVALID

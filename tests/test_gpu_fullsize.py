@@ -48,7 +48,7 @@ def test_512_cube_porosity06_16bit(prec):
     g = (1e-6, 0.0, 0.0)
     print(f"[case] 512^3 porosity 0.6 D3Q19 {prec}", flush=True)
     with tau1.Sim([tau1.Sample(geo.solid, drho, u)], lattice=19, precision=prec, g=g,
-                  graph_chunk=100, f16_scales=(18, 18)) as sim:
+                  graph_chunk=100) as sim:                      # default F16 scales
         sim.autotune(5)
         sim.step(2)
         idx = sample_nodes(geo.solid, 40000, seed=5)

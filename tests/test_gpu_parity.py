@@ -103,8 +103,7 @@ def test_small_random_reduced(q, prec, dims):
     solid, drho, u = inputs.random_state(nx, ny, nz, seed=2000 + nx + 7 * ny + 31 * nz)
     g = (1e-5, -2e-5, 3e-6)
     print(f"[case] small {prec} q={q} dims={dims}", flush=True)
-    sim, out = run_gpu([(solid, drho, u)], q, prec, g, 10, kernel=0,
-                       f16_scales=(18, 18))
+    sim, out = run_gpu([(solid, drho, u)], q, prec, g, 10, kernel=0)   # default F16 scales
     ref = run_oracle(q, solid, drho, u, g, 10)
     err = reduced_errors(out[0], ref, solid)
     print(f"[err] {prec} q={q} {dims} {err}", flush=True)
@@ -193,3 +192,23 @@ def test_runs_are_deterministic(kernel, prec):
             res.append((d.tobytes(), u.tobytes(), np.float64(k).tobytes(),
                         np.float64(m).tobytes()))
     assert res[0] == res[1]
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "f16"])
+def test_moments_physical_density(prec):
+    """tau1_moments reads back the physical density rho = 1 + (rho - 1),
+    formed in FP64 (1 at solid nodes), beside the same velocity as
+    tau1_moments_drho; in FP64 mode rho matches the oracle's 1 + drho."""
+    solid, drho, u = inputs.random_state(33, 9, 4, seed=91)
+    g = (1e-5, -2e-5, 3e-6)
+    print(f"[case] physical density {prec}", flush=True)
+    with tau1.Sim([tau1.Sample(solid, drho, u)], lattice=19, precision=prec, g=g) as sim:
+        sim.step(3)
+        d, u1 = sim.moments(0)
+        r, u2 = sim.rho_u(0)
+    assert np.array_equal(r, 1.0 + d)
+    assert np.array_equal(u1, u2)
+    assert (r[solid != 0] == 1.0).all()
+    if prec == "f64":
+        ref = run_oracle(19, solid, drho, u, g, 3)
+        assert np.abs(r - (1.0 + ref.drho)).max() <= TOL_F64

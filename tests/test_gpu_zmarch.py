@@ -67,7 +67,7 @@ def test_layouts_16bit(prec, dims):
     solid, drho, u = inputs.random_state(nx, ny, nz, seed=6000 + nx + ny)
     g = (1e-5, -2e-5, 3e-6)
     print(f"[case] zmarch {prec} dims={dims}", flush=True)
-    sim, out = run_gpu([(solid, drho, u)], 19, prec, g, 6, kernel=1, f16_scales=(18, 18))
+    sim, out = run_gpu([(solid, drho, u)], 19, prec, g, 6, kernel=1)   # default F16 scales
     ref = run_oracle(19, solid, drho, u, g, 6)
     err = reduced_errors(out[0], ref, solid)
     print(f"[err] {err}", flush=True)
