@@ -150,7 +150,9 @@ def gen_inputs(args, sections):
 
 
 def cpu_baseline(geo):
-    """FP64 oracle on the host cores: a few steps of the main lattice."""
+    """FP64 oracle on the host cores: a few steps of the main lattice; and on
+    one core, a few steps of a 32-plane slab of it."""
+    import numpy as np
     import oracle
     st = oracle.State(geo.solid)
     nf = geo.n_fluid
@@ -166,10 +168,27 @@ def cpu_baseline(geo):
     tn = time.perf_counter() - t
     cores = oracle.threads()
     log(f"oracle: {n} steps in {tn:.1f} s on {cores} threads")
+    # one thread: the first 32 z-planes of the same lattice (run periodic),
+    # one untimed step, then as many steps as take about 5 s
+    slab = oracle.State(np.ascontiguousarray(geo.solid[:32]))
+    nf1 = int((geo.solid[:32] == 0).sum())
+    slab = oracle.run(19, slab, G_MAIN, 1, nthreads=1)
+    t = time.perf_counter()
+    slab = oracle.run(19, slab, G_MAIN, 1, nthreads=1)
+    t1 = time.perf_counter() - t
+    n1 = int(max(1, min(20, round(5.0 / max(t1, 1e-3)))))
+    t = time.perf_counter()
+    oracle.run(19, slab, G_MAIN, n1, nthreads=1)
+    tn1 = time.perf_counter() - t
+    log(f"oracle, one thread: {n1} steps of the 512x512x32 slab in {tn1:.1f} s")
     return {"value": nf * n / tn / 1e9, "unit": "GFLUPS", "cores": cores, "kind": "oracle",
             "sample": f"{n} steps (after 4 untimed steps) of the full 512^3 porosity-0.7 "
                       f"D3Q19 lattice, FP64 oracle, OpenMP over z-planes, "
-                      f"{tn:.1f} s"}
+                      f"{tn:.1f} s",
+            "single_thread": {"value": nf1 * n1 / tn1 / 1e9, "unit": "GFLUPS", "cores": 1,
+                              "sample": f"{n1} steps (after 2 untimed steps) of the "
+                                        f"512x512x32 slab z < 32 of the same lattice, "
+                                        f"run periodic, one thread, {tn1:.1f} s"}}
 
 
 class GpuRunner:
@@ -358,6 +377,24 @@ def chunk_stats(solid, k):
             "r_mixed": float((stored & ~pure).sum()) / max(n_st, 1)}
 
 
+def bandwidth_model(rows, b_max):
+    """The paper's bandwidth model for porous media (Eq. 13, Section 4.3):
+    B_est = phi_chunk B_max / (1 + delta_p R_mixed / 2), with B_max the copy
+    kernel's rate and delta_p the latency penalty of a mixed chunk relative to
+    its transfer time.  delta_p is fitted by least squares to the measured
+    fluid-node bandwidth B (the algorithmic rate, fluid nodes only, as the
+    paper counts it) through phi_chunk B_max / B - 1 = delta_p R_mixed / 2;
+    returns delta_p and writes b_est, b_chunk_only (phi_chunk B_max) per row."""
+    xs = [r["r_mixed"] / 2.0 for r in rows]
+    ys = [r["phi_chunk"] * b_max / r["packed"]["alg_gbs"] - 1.0 for r in rows]
+    den = sum(x * x for x in xs)
+    delta = sum(x * y for x, y in zip(xs, ys)) / den if den > 0 else 0.0
+    for r in rows:
+        r["b_est_gbs"] = r["phi_chunk"] * b_max / (1.0 + delta * r["r_mixed"] / 2.0)
+        r["b_chunk_only_gbs"] = r["phi_chunk"] * b_max
+    return delta
+
+
 def porosity_section(gr, geos, args, out):
     from paper_2312_14742_amd import tau1
     rows = []
@@ -378,11 +415,19 @@ def porosity_section(gr, geos, args, out):
         moved = 2 * 16 * row["stored_chunk_frac"] * geo.solid.size
         row["packed"]["stored_gbs"] = moved / (row["packed"]["launch_ms"] * 1e-3) / 1e9
         rows.append(row)
+    # B_max: the copy kernel over the bytes of a dense FP32 state of this size
+    # (read and write 16 B per node), as the paper takes its copy rate
+    b_max = gr.copy_gbs(2 * 16 * geos[0].solid.size)
+    delta = bandwidth_model(rows, b_max)
+    log(f"porosity model (Eq. 13): B_max {b_max:.0f} GB/s, fitted delta_p {delta:.3f}")
     out["porosity_sweep"] = {
         "workload": "D3Q19 FP32, 256^3 periodic sphere packings, r=8, target porosity "
                     "0.05..0.9, seeds 2000+i, g=1e-6 x, "
                     f"{args.porosity_steps} steps per case; the working set (0.3-0.5 GB "
                     "packed) is of the order of the 256 MB last-level cache",
+        "bandwidth_model": {"equation": "B_est = phi_chunk B_max / (1 + delta_p R_mixed / 2)",
+                            "b_max_gbs": b_max, "delta_p_fitted": delta,
+                            "measured": "packed alg_gbs (fluid-node bytes per launch time)"},
         "cases": rows}
 
 

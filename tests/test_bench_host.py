@@ -53,3 +53,18 @@ def test_counter_profile_matches_kernel_sources():
     assert cnt["source_sha256"] == bench.kernel_source_hash()
     for tile in (13, 14, 15):
         assert float(cnt[f"hbm_bytes_per_launch_tile{tile}"]) > 0
+
+
+def test_bandwidth_model_recovers_its_penalty():
+    """Rates generated from Eq. (13) with a known delta_p give that delta_p
+    back, and B_est then equals the generated rates."""
+    b_max, delta = 6000.0, 1.7
+    rows = []
+    for phi_c, r in ((0.58, 0.97), (0.7, 0.85), (0.88, 0.45), (0.97, 0.12)):
+        b = phi_c * b_max / (1.0 + delta * r / 2.0)
+        rows.append({"phi_chunk": phi_c, "r_mixed": r, "packed": {"alg_gbs": b}})
+    got = bench.bandwidth_model(rows, b_max)
+    assert abs(got - delta) <= 1e-12
+    for row in rows:
+        assert abs(row["b_est_gbs"] - row["packed"]["alg_gbs"]) <= 1e-9 * row["b_est_gbs"]
+        assert row["b_chunk_only_gbs"] == row["phi_chunk"] * b_max

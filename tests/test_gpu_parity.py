@@ -175,17 +175,18 @@ def test_reductions_vs_oracle(prec):
     sim.close()
 
 
-@pytest.mark.parametrize("kernel,prec", [(0, "f64"), (1, "f32"), (3, "f32"), (1, "bf16")])
+@pytest.mark.parametrize("kernel,prec", [(0, "f64"), (0, "f32"), (1, "f32"), (1, "bf16")])
 def test_runs_are_deterministic(kernel, prec):
     """Two contexts over the same inputs give the same bits: state, mass and
-    permeability (no atomics in the step; the reductions use a fixed tree)."""
+    permeability (no atomics in the step; the reductions use a fixed order of
+    lane shuffles and wave sums)."""
     geo = inputs.spheres(64, 48, 40, 5.0, 0.6, seed=31)
     g = (1e-5, 2e-6, 0.0)
     print(f"[case] determinism kernel={kernel} {prec}", flush=True)
     res = []
     for _ in range(2):
         with tau1.Sim([tau1.Sample(geo.solid)], lattice=19, precision=prec, g=g,
-                      kernel=kernel, layout=0 if kernel == 3 else -1, graph_chunk=10) as sim:
+                      kernel=kernel, graph_chunk=10) as sim:
             sim.step(37)
             d, u = sim.moments(0)
             k, m = sim.permeability(0, 0)
