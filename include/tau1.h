@@ -215,6 +215,23 @@ tau1_status tau1_moments_drho(tau1_ctx *ctx, int32_t sample, double *drho,
 tau1_status tau1_permeability(tau1_ctx *ctx, int32_t sample,
                               int32_t axis, double *k, double *mass);
 
+/* For callers that cannot allocate device memory or synchronise (code under
+ * HIP graph capture, tight serving loops): the reductions of
+ * tau1_permeability, enqueued on the context's stream without waiting.  The
+ * block partials live in a static device array of this library (32 KiB per
+ * GPU, held until the process ends; it serves every sample size, since the
+ * partial count is fixed), so the call allocates nothing, sets no memory and
+ * copies nothing to the host.  out: caller-owned device memory of 4 doubles,
+ * 8-byte aligned, written when the stream reaches the call: out[0] = mass,
+ * out[1] = k (0 when g[axis] == 0), out[2] = fluid node count, out[3] =
+ * count of fluid nodes holding NaN or Inf.  Results are bit-for-bit those of
+ * tau1_permeability.  Calls on one GPU share the array: calls that overlap in
+ * time on that GPU (other streams, other threads) race and must not be
+ * issued.  TAU1_E_INVALID for a bad sample, axis or out; TAU1_E_HIP if the
+ * array's device address could not be found. */
+tau1_status tau1_permeability_noalloc(tau1_ctx *ctx, int32_t sample,
+                                      int32_t axis, double *out);
+
 /* Times each eligible step-kernel shape for trial_steps steps (state is not
  * advanced: trials write only the spare buffer), keeps the fastest and, if
  * the descriptor named a cache file, records it there.  Synchronous.  An

@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -246,6 +247,41 @@ Plan make_plan(const tau1_desc* d, bool tables) {
 
 }  // namespace
 
+// Device scratch of tau1_permeability_noalloc: the reduction's block
+// partials, kReduceBlocks x 4 doubles = 32 KiB.  Each GPU the library runs on
+// holds its own copy until the process ends.  In host code the name stands
+// for no device address: kernels get the address that hipGetSymbolAddress
+// reports for the current device (scratch_on_device).
+constexpr int kScratchDoubles = kReduceBlocks * 4;
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+// Address of `scratch` on the current device, looked up once per device (at
+// the first tau1_create on it); nullptr if the lookup failed.
+double* scratch_on_device() {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) == hipSuccess && p)
+            g_scratch_ptr[dev] = static_cast<double*>(p);
+        else
+            (void)hipGetLastError();
+    }
+    return g_scratch_ptr[dev];
+}
+
+}  // namespace
+
 struct tau1_ctx {
     int lattice = 19, precision = kF32, nsamples = 1;
     int graph_chunk = 100;
@@ -272,6 +308,7 @@ struct tau1_ctx {
     double g[3] = {0, 0, 0};
     std::string cache;
     hipError_t last_hip = hipSuccess;
+    double* scratch = nullptr;  // this context's device's copy of `scratch`
 };
 
 namespace {
@@ -576,17 +613,37 @@ tau1_status export_sample_t(tau1_ctx* ctx, int s, double* drho, double* u, int* 
     return TAU1_OK;
 }
 
+// Enqueues the two reduction kernels of one sample: block partials into
+// `partial` (kReduceBlocks x 4 doubles, every entry written), then the four
+// results into `res`.
 template <int P>
-tau1_status reduce_t(tau1_ctx* ctx, int s, int axis, double out[4]) {
+tau1_status reduce_launch_t(tau1_ctx* ctx, int s, int axis, double* partial, double* res) {
     const SampleDev& sd = ctx->plan.s[s].dev;
-    double* partial = reinterpret_cast<double*>(ctx->base + ctx->plan.partial_off);
-    double* res = partial + kReduceBlocks * 4;
     hipLaunchKernelGGL(k_reduce_partial<P>, dim3(kReduceBlocks), dim3(kReduceThreads), 0,
                        ctx->stream, ctx->args[ctx->parity], s, axis, partial);
     HIP_TRY(hipGetLastError());
     hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(kReduceThreads), 0, ctx->stream, partial,
                        sd.n, ctx->g[axis], res);
     HIP_TRY(hipGetLastError());
+    return TAU1_OK;
+}
+
+tau1_status reduce_launch(tau1_ctx* ctx, int s, int axis, double* partial, double* res) {
+    switch (ctx->precision) {
+        case kF64: return reduce_launch_t<kF64>(ctx, s, axis, partial, res);
+        case kF32: return reduce_launch_t<kF32>(ctx, s, axis, partial, res);
+        case kF16: return reduce_launch_t<kF16>(ctx, s, axis, partial, res);
+        case kBF16: return reduce_launch_t<kBF16>(ctx, s, axis, partial, res);
+    }
+    return TAU1_E_INVALID;
+}
+
+// tau1_permeability's reduction: partials and results in the workspace.
+tau1_status reduce_ws(tau1_ctx* ctx, int s, int axis, double out[4]) {
+    double* partial = reinterpret_cast<double*>(ctx->base + ctx->plan.partial_off);
+    double* res = partial + kReduceBlocks * 4;
+    const tau1_status st = reduce_launch(ctx, s, axis, partial, res);
+    if (st != TAU1_OK) return st;
     HIP_TRY(hipMemcpyAsync(out, res, sizeof(double) * 4, hipMemcpyDeviceToHost, ctx->stream));
     HIP_TRY(hipStreamSynchronize(ctx->stream));
     return TAU1_OK;
@@ -734,6 +791,8 @@ tau1_status tau1_create(const tau1_desc* desc, tau1_ctx** out) {
         delete ctx;
         return TAU1_E_WORKSPACE;
     }
+    // the allocation-free reduction's scratch on this device (once per device)
+    ctx->scratch = scratch_on_device();
     ctx->lattice = desc->lattice;
     ctx->precision = desc->precision;
     ctx->nsamples = desc->n_samples;
@@ -910,18 +969,27 @@ tau1_status tau1_permeability(tau1_ctx* ctx, int32_t sample, int32_t axis, doubl
     if (sample < 0 || sample >= ctx->nsamples || axis < 0 || axis > 2) return TAU1_E_INVALID;
     if (k && ctx->g[axis] == 0.0) return TAU1_E_INVALID;
     double res[4] = {0, 0, 0, 0};
-    switch (ctx->precision) {
-        case kF64: st = reduce_t<kF64>(ctx, sample, axis, res); break;
-        case kF32: st = reduce_t<kF32>(ctx, sample, axis, res); break;
-        case kF16: st = reduce_t<kF16>(ctx, sample, axis, res); break;
-        case kBF16: st = reduce_t<kBF16>(ctx, sample, axis, res); break;
-    }
+    st = reduce_ws(ctx, sample, axis, res);
     if (st != TAU1_OK) return st;
     if (res[3] != 0.0 || !std::isfinite(res[0]) || !std::isfinite(res[1]))
         return TAU1_E_NONFINITE;
     if (k) *k = res[1];
     if (mass) *mass = res[0];
     return TAU1_OK;
+}
+
+tau1_status tau1_permeability_noalloc(tau1_ctx* ctx, int32_t sample, int32_t axis,
+                                      double* out) {
+    tau1_status st = check_usable(ctx);
+    if (st != TAU1_OK) return st;
+    if (sample < 0 || sample >= ctx->nsamples || axis < 0 || axis > 2) return TAU1_E_INVALID;
+    if (!out || reinterpret_cast<uintptr_t>(out) % alignof(double) != 0) return TAU1_E_INVALID;
+    if (!ctx->scratch) return TAU1_E_HIP;  // the device copy of `scratch` was not found
+    // the partial count is fixed (kReduceBlocks), so every sample fits
+    static_assert(kReduceBlocks * 4 <= kScratchDoubles, "scratch holds every partial");
+    // every partial is written before the final pass reads it, so nothing is
+    // cleared; the final pass writes the four results straight to `out`
+    return reduce_launch(ctx, sample, axis, ctx->scratch, out);
 }
 
 tau1_status tau1_autotune(tau1_ctx* ctx, int32_t trial_steps) {

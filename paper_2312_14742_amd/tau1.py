@@ -28,7 +28,8 @@ TAU1_E_WORKSPACE = -6
 
 # Every function the header declares (checked against include/tau1.h by the tests).
 EXPORTS = ("tau1_workspace_size", "tau1_create", "tau1_step", "tau1_sync",
-           "tau1_moments", "tau1_moments_drho", "tau1_permeability", "tau1_autotune",
+           "tau1_moments", "tau1_moments_drho", "tau1_permeability",
+           "tau1_permeability_noalloc", "tau1_autotune",
            "tau1_get_info", "tau1_destroy", "tau1_strerror", "tau1_copy_probe")
 
 
@@ -103,6 +104,8 @@ def _lib() -> ctypes.CDLL:
                                           ctypes.POINTER(ctypes.c_double),
                                           ctypes.POINTER(ctypes.c_double)]
         lib.tau1_permeability.restype = st
+        lib.tau1_permeability_noalloc.argtypes = [P, ctypes.c_int32, ctypes.c_int32, P]
+        lib.tau1_permeability_noalloc.restype = st
         lib.tau1_autotune.argtypes = [P, ctypes.c_int32]
         lib.tau1_autotune.restype = st
         lib.tau1_get_info.argtypes = [P, ctypes.POINTER(tau1_info)]
@@ -279,6 +282,17 @@ class Sim:
                                         ctypes.byref(k) if with_k else None,
                                         ctypes.byref(m)), "tau1_permeability")
         return (k.value if with_k else None), m.value
+
+    def permeability_noalloc(self, out, sample: int = 0, axis: int = 0):
+        """Enqueue the FP64 reductions with no allocation and no wait; ``out`` is
+        a float64 device tensor of at least 4 elements that receives (mass, k,
+        fluid count, non-finite count) when the stream gets there."""
+        if out.dtype != self._torch.float64 or not out.is_cuda or out.numel() < 4 \
+                or not out.is_contiguous():
+            raise ValueError("out must be a contiguous float64 device tensor of >= 4 elements")
+        _check(_lib().tau1_permeability_noalloc(self._c(), int(sample), int(axis),
+                                                out.data_ptr()),
+               "tau1_permeability_noalloc")
 
     def autotune(self, trial_steps: int = 10):
         _check(_lib().tau1_autotune(self._c(), int(trial_steps)), "tau1_autotune")
