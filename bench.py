@@ -203,10 +203,10 @@ class GpuRunner:
         torch.cuda.set_device(self.device)
 
     def make(self, samples, lattice, precision, g, graph_chunk, tile, kernel=-1,
-             f16_scales=(0, 0), layout=-1):
+             f16_scales=(0, 0), layout=-1, batch_graph=0):
         sim = self.tau1.Sim(samples, lattice=lattice, precision=precision, g=g,
                             graph_chunk=graph_chunk, kernel=kernel, tile=tile,
-                            f16_scales=f16_scales, layout=layout)
+                            f16_scales=f16_scales, layout=layout, batch_graph=batch_graph)
         if tile < 0 and kernel != 0:
             sim.autotune(10)
         return sim
@@ -230,9 +230,9 @@ class GpuRunner:
         return wall, ev
 
     def case(self, samples, lattice, precision, steps, warmup, graph_chunk, tile,
-             g=G_MAIN, label="", layout=-1, repeats=1, kernel=-1):
+             g=G_MAIN, label="", layout=-1, repeats=1, kernel=-1, batch_graph=0):
         sim = self.make(samples, lattice, precision, g, graph_chunk, tile, kernel=kernel,
-                        layout=layout)
+                        layout=layout, batch_graph=batch_graph)
         wall, ev = self.time_steps(sim, steps, warmup)
         inf = sim.info()
         walls = [wall] + [self.time_steps(sim, steps, 0)[0] for _ in range(repeats - 1)]
@@ -278,7 +278,16 @@ def precision_section(gr, geo, args, out):
         sim, res = gr.case([tau1.Sample(geo.solid)], 19, prec, args.precision_steps,
                            args.warmup, args.graph_chunk, -1, label=f"precision {prec}")
         sim.close()
+        if prec != "f32":
+            # the dense layout (tiles 0-11) beside the default packed one
+            sim, rd = gr.case([tau1.Sample(geo.solid)], 19, prec, args.precision_steps,
+                              args.warmup, args.graph_chunk, -1, label=f"precision {prec} dense",
+                              layout=0)
+            sim.close()
+            res["dense_layout"] = {k: rd[k] for k in ("gflups", "alg_gbs", "frac", "tile")}
         modes[prec] = res
+    modes["ratio_16bit_over_f32"] = {p: modes[p]["gflups"] / modes["f32"]["gflups"]
+                                     for p in ("f16", "bf16")}
     # accuracy on the 128^3 crop of the same mask (run periodic), 2000 steps
     crop = np.ascontiguousarray(geo.solid[:128, :128, :128])
     fluid = crop == 0
@@ -311,11 +320,19 @@ def batch_section(gr, batch, args, out):
     from paper_2312_14742_amd import tau1
     samples = [tau1.Sample(b.geometry.solid) for b in batch]
     steps = args.batch_steps
+    # the default graph (one chain per lane layout, side by side) and, for
+    # comparison, the launches of a step in one chain
     sim, res = gr.case(samples, 19, "f32", steps, args.graph_chunk, args.graph_chunk,
-                       args.tile, label="batched 64 samples")
+                       args.tile, label="batched 64 samples, chains per layout")
     probe = [0, max(range(len(batch)), key=lambda i: batch[i].side)]
     batched_state = {i: sim.moments(i) for i in probe}
     sim.close()
+    sim2, res2 = gr.case(samples, 19, "f32", steps, args.graph_chunk, args.graph_chunk,
+                         args.tile, label="batched 64 samples, one chain", batch_graph=1)
+    sim2.close()
+    res["graph"] = "one chain of launches per lane layout, the chains side by side"
+    res["one_chain"] = {k: res2[k] for k in ("gflups", "alg_gbs", "frac", "tile",
+                                             "ms_per_step")}
     if args.no_batch_solo:
         out["batched"] = res
         return

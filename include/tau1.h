@@ -39,8 +39,8 @@
  * consecutive x-nodes (the z-march lane chunks, K fixed by nx) that hold at
  * least one fluid node, so the state is smaller and a step moves fewer bytes.
  * Packing applies to the samples whose nx has a one-row-per-wave z-march
- * layout (nx = 64, 128, 192, 256, 320, 384, 512); the other samples of the
- * context stay dense.
+ * layout (nx = 64, 96, 128, 160, 192, 224, 256, 288, 320, 384, 512); the
+ * other samples of the context stay dense.
  */
 #ifndef TAU1_H
 #define TAU1_H
@@ -122,9 +122,9 @@ typedef struct {
     int32_t f16_log2_scale_u;   /* F16 scale of the stored velocity u + g/2,
                                    0 = 16; same range and check as above    */
     const char *tune_cache; /* path of the autotune JSON cache, or NULL         */
-    int32_t layout;         /* state layout: -1 = automatic (packed for F32
-                               z-march contexts unless tile is 0-11, dense
-                               otherwise), 0 = dense, 1 = packed
+    int32_t layout;         /* state layout: -1 = automatic (packed for F32,
+                               F16 and BF16 z-march contexts unless tile is
+                               0-11, dense otherwise), 0 = dense, 1 = packed
                                (TAU1_E_UNSUPPORTED if no sample can be
                                packed: F64, kernel 0, other nx)            */
     /* D2Q9 only (TAU1_E_UNSUPPORTED on the 3-D lattices when set).  Solid
@@ -136,6 +136,13 @@ typedef struct {
                                rho_in, at x = nx - 1 rho_out (nx >= 3)      */
     double rho_in, rho_out; /* > 0, used when x_boundary = 1              */
     double wall_u[3];       /* velocity of the moving walls (z ignored)    */
+    /* Graph shape of a batch whose samples need several z-march launches per
+     * step (one per lane layout): 1 = one chain: the launches of a step run
+     * one after another, largest first, each with the whole GPU; 2 = one
+     * chain per lane layout, the chains running side by side; 0 = automatic
+     * (2, measured the faster on the 64-sample batch).  Single-launch
+     * contexts ignore it.                                                   */
+    int32_t batch_graph;
 } tau1_desc;
 
 /* Static facts about a created context (host copy). */

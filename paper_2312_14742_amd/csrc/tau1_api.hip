@@ -71,6 +71,7 @@ tau1_status validate(const tau1_desc* d) {
     if (d->tile < -1 || d->tile >= kNumTiles) return TAU1_E_INVALID;
     if (d->layout < -1 || d->layout > 1) return TAU1_E_INVALID;
     if (d->x_boundary < 0 || d->x_boundary > 1) return TAU1_E_INVALID;
+    if (d->batch_graph < 0 || d->batch_graph > 2) return TAU1_E_INVALID;
     for (int a = 0; a < 3; ++a)
         if (!std::isfinite(d->wall_u[a])) return TAU1_E_INVALID;
     if (d->x_boundary == 1 &&
@@ -117,7 +118,10 @@ int64_t chunk_table(const tau1_sample& in, int k, int groups, uint32_t* tab) {
         for (int g = 0; g < groups; ++g) {
             uint64_t bits = 0;
             for (int l = 0; l < 64; ++l) {
-                const uint8_t* ch = row + (int64_t)(g * 64 + l) * k;
+                // lanes past the row's end (layouts with idle lanes) hold no chunk
+                const int64_t x0 = (int64_t)(g * 64 + l) * k;
+                if (x0 >= in.nx) break;
+                const uint8_t* ch = row + x0;
                 bool fluid = false;
                 for (int j = 0; j < k; ++j) fluid |= ch[j] == 0;
                 bits |= (uint64_t)fluid << l;
@@ -163,12 +167,12 @@ Plan make_plan(const tau1_desc* d, bool tables) {
         if (d->lattice == 9) sd.variant = -1;  // the D2Q9 kernel only
         maxn = std::max<int64_t>(maxn, sd.n);
     }
-    // packed layout: by default for FP32 (there the step is bound by memory
-    // traffic) unless a dense-layout tile is asked for, for any z-march
-    // precision on request; one-row-per-wave lane layouts only, and only
-    // where the z-march kernel runs
+    // packed layout: by default for the z-march precisions (FP32 and the
+    // 16-bit storage modes) unless a dense-layout tile is asked for;
+    // one-row-per-wave lane layouts only, and only where the z-march kernel
+    // runs
     const bool zm = zmarch_supported(d->lattice, d->precision, p.s.data(), d->n_samples);
-    const bool auto_pack = d->precision == kF32 && (d->tile < 0 || tile_mode(d->tile) == 3);
+    const bool auto_pack = d->precision != kF64 && (d->tile < 0 || tile_mode(d->tile) == 3);
     const bool pack = zm && (d->kernel == -1 || d->kernel == 1) &&
                       (d->layout == 1 || (d->layout < 0 && auto_pack));
     // All samples of one lane layout share a launch, so a layout is packed
@@ -305,6 +309,7 @@ struct tau1_ctx {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     int graph_kernel = -1, graph_tile = -1, graph_parity = -1;
+    bool graph_chains = false;  // batch graphs: one chain per lane layout (else one chain)
     double g[3] = {0, 0, 0};
     std::string cache;
     hipError_t last_hip = hipSuccess;
@@ -413,34 +418,56 @@ void destroy_graph(tau1_ctx* ctx) {
     ctx->graph_kernel = ctx->graph_tile = -1;
 }
 
-// Graph of graph_chunk time steps: one chain of single-step kernel nodes per
-// launch group (z-march lane layout); the chains share no samples, so they
-// are independent of each other.  The parity alternates node by node and,
+// Graph of graph_chunk time steps.  The parity alternates step by step and,
 // graph_chunk being even, the graph maps the current buffer onto itself.
+// A context with several launch groups (a batch of several z-march lane
+// layouts) either runs them as one chain -- the launches of a step one after
+// another, each with the whole GPU -- or as one chain per group, the chains
+// side by side (the groups share no samples, so they are independent).
 // Built without stream capture.
 tau1_status build_graph(tau1_ctx* ctx) {
     destroy_graph(ctx);
     HIP_TRY(hipGraphCreate(&ctx->graph, 0));
     const int ng = launch_groups(ctx, ctx->kernel);
+    std::vector<Launch> ls;
     for (int g = 0; g < ng; ++g) {
-        const Launch l = step_launch(ctx, ctx->kernel, ctx->tile, g);
-        if (!l.fn) return TAU1_E_UNSUPPORTED;
-        if (l.grid.x == 0) continue;
-        hipGraphNode_t prev = nullptr;
-        for (int s = 0; s < ctx->graph_chunk; ++s) {
-            void* params[] = {launch_args(ctx, ctx->kernel, g, (ctx->parity + s) & 1)};
-            hipKernelNodeParams kp{};
-            kp.func = l.fn;
-            kp.gridDim = l.grid;
-            kp.blockDim = l.block;
-            kp.sharedMemBytes = (unsigned)l.shmem;
-            kp.kernelParams = params;
-            kp.extra = nullptr;
-            hipGraphNode_t node;
-            HIP_TRY(hipGraphAddKernelNode(&node, ctx->graph, prev ? &prev : nullptr, prev ? 1 : 0,
-                                          &kp));
-            prev = node;
+        ls.push_back(step_launch(ctx, ctx->kernel, ctx->tile, g));
+        if (!ls.back().fn) return TAU1_E_UNSUPPORTED;
+    }
+    auto add = [&](int g, int s, hipGraphNode_t* prev) -> tau1_status {
+        const Launch& l = ls[g];
+        void* params[] = {launch_args(ctx, ctx->kernel, g, (ctx->parity + s) & 1)};
+        hipKernelNodeParams kp{};
+        kp.func = l.fn;
+        kp.gridDim = l.grid;
+        kp.blockDim = l.block;
+        kp.sharedMemBytes = (unsigned)l.shmem;
+        kp.kernelParams = params;
+        kp.extra = nullptr;
+        hipGraphNode_t node;
+        HIP_TRY(hipGraphAddKernelNode(&node, ctx->graph, *prev ? prev : nullptr, *prev ? 1 : 0,
+                                      &kp));
+        *prev = node;
+        return TAU1_OK;
+    };
+    if (ctx->graph_chains || ng == 1) {
+        for (int g = 0; g < ng; ++g) {
+            if (ls[g].grid.x == 0) continue;
+            hipGraphNode_t prev = nullptr;
+            for (int s = 0; s < ctx->graph_chunk; ++s) {
+                const tau1_status st = add(g, s, &prev);
+                if (st != TAU1_OK) return st;
+            }
         }
+    } else {
+        // groups in the order of launch_one (largest work first)
+        hipGraphNode_t prev = nullptr;
+        for (int s = 0; s < ctx->graph_chunk; ++s)
+            for (int g = 0; g < ng; ++g) {
+                if (ls[g].grid.x == 0) continue;
+                const tau1_status st = add(g, s, &prev);
+                if (st != TAU1_OK) return st;
+            }
     }
     HIP_TRY(hipGraphInstantiate(&ctx->exec, ctx->graph, nullptr, nullptr, 0));
     ctx->graph_kernel = ctx->kernel;
@@ -652,12 +679,18 @@ tau1_status reduce_ws(tau1_ctx* ctx, int s, int axis, double out[4]) {
 // Selects the z-march tile (z-segment length), rebuilds and uploads the work
 // list; cached graphs are rebuilt on the next step.
 tau1_status set_tile(tau1_ctx* ctx, int tile) {
-    // lane layouts present, in order of first appearance
+    // lane layouts present, the one with the most fluid nodes first (the
+    // order of the launches of a step when they run one after another)
     std::vector<int> layouts;
-    for (const auto& sh : ctx->plan.s)
-        if (sh.dev.variant >= 0 &&
-            std::find(layouts.begin(), layouts.end(), sh.dev.variant) == layouts.end())
+    std::vector<int64_t> work(kNumVariants, 0);
+    for (const auto& sh : ctx->plan.s) {
+        if (sh.dev.variant < 0) continue;
+        if (std::find(layouts.begin(), layouts.end(), sh.dev.variant) == layouts.end())
             layouts.push_back(sh.dev.variant);
+        work[sh.dev.variant] += sh.n_fluid;
+    }
+    std::stable_sort(layouts.begin(), layouts.end(),
+                     [&](int a, int b) { return work[a] > work[b]; });
     std::vector<int32_t> tl;
     std::vector<tau1_ctx::ZGroup> groups;
     for (int v : layouts) {
@@ -801,6 +834,7 @@ tau1_status tau1_create(const tau1_desc* desc, tau1_ctx** out) {
     ctx->base = reinterpret_cast<uint8_t*>(desc->workspace);
     ctx->ws_bytes = desc->workspace_bytes;
     ctx->cache = desc->tune_cache ? desc->tune_cache : "";
+    ctx->graph_chains = desc->batch_graph != 1;
     for (int a = 0; a < 3; ++a) ctx->g[a] = desc->g[a];
 
     const int lsr = f16_log2_scale(desc->f16_log2_scale_rho);

@@ -183,7 +183,7 @@ __device__ __forceinline__ int64_t state_slot(const uint8_t* base, const SampleD
                                               int y, int z, int64_t i) {
     if (sd.pk == 0) return i;
     const int ci = x / sd.pk;
-    const int groups = sd.nx / (64 * sd.pk);
+    const int groups = (sd.nx + 64 * sd.pk - 1) / (64 * sd.pk);  // a last group may be partial
     const uint4 e = reinterpret_cast<const uint4*>(base + sd.chunk_tab)
         [((int64_t)z * sd.ny + y) * groups + (ci >> 6)];
     const uint64_t bits = ((uint64_t)e.y << 32) | e.x;

@@ -76,32 +76,48 @@ constexpr bool zr_roll(int g, int mode) { return mode == 2 || ((mode == 1 || mod
 // Packed-layout rows (mode 3 exists only for one-row-per-wave layouts).
 constexpr bool zr_packed(int g, int mode) { return mode == 3 && g == 1; }
 
-// Lane layouts (G, C, K) compiled into the kernel; nx = C * (64 / G) * K.
+// Lane layouts (G, C, K, L) compiled into the kernel: G rows per wave, each
+// row in C chunks of L lanes x K nodes, nx = C * L * K.  L = 64 / G for the
+// full layouts; the one-row layouts with L < 64 leave lanes L..63 idle (they
+// load and store nothing) so that rows of 96, 160, 224 and 288 nodes get the
+// one-row-per-wave schedules (rows shared through LDS, packed state) too.
 struct ZrVariant {
-    int g, c, k;
+    int g, c, k, l;
 };
 constexpr int kNumVariants = 15;
 constexpr ZrVariant kVariants[kNumVariants] = {
-    {1, 1, 1}, {1, 1, 2}, {1, 1, 3}, {1, 1, 4}, {1, 1, 5}, {1, 2, 3}, {1, 2, 4},
-    {2, 1, 1}, {2, 1, 3}, {2, 1, 5}, {2, 1, 7}, {2, 3, 3},
-    {4, 1, 1}, {4, 1, 3}, {4, 1, 5}};
+    {1, 1, 1, 64}, {1, 1, 2, 64}, {1, 1, 3, 64}, {1, 1, 4, 64}, {1, 1, 5, 64}, {1, 2, 3, 64},
+    {1, 2, 4, 64}, {2, 1, 1, 32}, {1, 1, 2, 48}, {1, 1, 4, 40}, {1, 1, 4, 56}, {1, 1, 6, 48},
+    {4, 1, 1, 16}, {4, 1, 3, 16}, {4, 1, 5, 16}};
+
+constexpr int zr_nx(const ZrVariant& v) { return v.c * v.l * v.k; }
 
 inline int zr_variant_for(int nx) {
     for (int v = 0; v < kNumVariants; ++v)
-        if (kVariants[v].c * (64 / kVariants[v].g) * kVariants[v].k == nx) return v;
+        if (zr_nx(kVariants[v]) == nx) return v;
     return -1;
 }
 
 // ---------------------------------------------------------------------------
-// Lane moves inside a lane group of Lg = 64 / G lanes.
+// Lane moves inside a lane group of L lanes (64 / G, or fewer for a one-row
+// layout with idle lanes).
 // up(v):   lane gl receives v from lane gl - 1 (wrapping), i.e. data moves +x
 // down(v): lane gl receives v from lane gl + 1 (wrapping), data moves -x
+// Per-lane facts the moves need: the first and last lane of the group, and
+// for L < 64 the byte addresses of the source lanes of a crossbar permute.
 // ---------------------------------------------------------------------------
-template <int G>
-__device__ __forceinline__ float lane_up(float v) {
+struct ZrLanes {
+    bool first, last;
+    int up, down;
+};
+
+template <int G, int NL>
+__device__ __forceinline__ float lane_up(float v, const ZrLanes& ln) {
     const int iv = __builtin_bit_cast(int, v);
     int r;
-    if constexpr (G == 1) {
+    if constexpr (G == 1 && NL < 64) {
+        r = __builtin_amdgcn_ds_bpermute(ln.up, iv);
+    } else if constexpr (G == 1) {
         r = __builtin_amdgcn_update_dpp(0, iv, 0x13C, 0xf, 0xf, false);  // wave_ror:1
     } else if constexpr (G == 4) {
         r = __builtin_amdgcn_update_dpp(0, iv, 0x121, 0xf, 0xf, false);  // row_ror:1
@@ -113,11 +129,13 @@ __device__ __forceinline__ float lane_up(float v) {
     return __builtin_bit_cast(float, r);
 }
 
-template <int G>
-__device__ __forceinline__ float lane_down(float v) {
+template <int G, int NL>
+__device__ __forceinline__ float lane_down(float v, const ZrLanes& ln) {
     const int iv = __builtin_bit_cast(int, v);
     int r;
-    if constexpr (G == 1) {
+    if constexpr (G == 1 && NL < 64) {
+        r = __builtin_amdgcn_ds_bpermute(ln.down, iv);
+    } else if constexpr (G == 1) {
         r = __builtin_amdgcn_update_dpp(0, iv, 0x134, 0xf, 0xf, false);  // wave_rol:1
     } else if constexpr (G == 4) {
         r = __builtin_amdgcn_update_dpp(0, iv, 0x12F, 0xf, 0xf, false);  // row_ror:15
@@ -308,9 +326,9 @@ __device__ __forceinline__ void add_to(Planes<PX>& pl, int slot, float w, float 
 // (c, j) sends to (c, j + c_x); across a lane boundary the value rotates one
 // lane inside the group, and the group's first/last lane takes it from the
 // neighbouring chunk (the node after the last of chunk c is the first of c+1).
-template <int Q, int KD, int G, int C, int K>
+template <int Q, int KD, int G, int C, int K, int NL>
 __device__ __forceinline__ void push_dir(Planes<C * K>& pl, const Src (&s)[C * K], int zmask,
-                                         bool first_lane, bool last_lane) {
+                                         const ZrLanes& ln) {
     using L = Lattice<Q>;
     constexpr int CX = L::c[KD].x, CY = L::c[KD].y, CZ = L::c[KD].z;
     if (!((zmask >> (CZ + 1)) & 1)) return;
@@ -325,9 +343,9 @@ __device__ __forceinline__ void push_dir(Planes<C * K>& pl, const Src (&s)[C * K
             if (dst >= 0 && dst < K) {
                 add_to<CX, CY, CZ, C * K>(pl, c * K + dst, w, u);
             } else if (dst == K) {
-                edge[c] = lane_up<G>(u);
+                edge[c] = lane_up<G, NL>(u, ln);
             } else {
-                edge[c] = lane_down<G>(u);
+                edge[c] = lane_down<G, NL>(u, ln);
             }
         }
     }
@@ -336,21 +354,21 @@ __device__ __forceinline__ void push_dir(Planes<C * K>& pl, const Src (&s)[C * K
         for (int c = 0; c < C; ++c) {
             float v = edge[c];
             if constexpr (C > 1) {
-                if constexpr (CX > 0) v = first_lane ? edge[(c + C - 1) % C] : v;
-                else v = last_lane ? edge[(c + 1) % C] : v;
+                if constexpr (CX > 0) v = ln.first ? edge[(c + C - 1) % C] : v;
+                else v = ln.last ? edge[(c + 1) % C] : v;
             }
             add_to<CX, CY, CZ, C * K>(pl, CX > 0 ? c * K : c * K + K - 1, w, v);
         }
     }
 }
 
-template <int Q, int CYSEL, int G, int C, int K, int KD = 1>
+template <int Q, int CYSEL, int G, int C, int K, int NL, int KD = 1>
 __device__ __forceinline__ void push_row(Planes<C * K>& pl, const Src (&s)[C * K], int zmask,
-                                         bool first_lane, bool last_lane) {
+                                         const ZrLanes& ln) {
     if constexpr (KD < Q) {
         if constexpr (Lattice<Q>::c[KD].y == CYSEL)
-            push_dir<Q, KD, G, C, K>(pl, s, zmask, first_lane, last_lane);
-        push_row<Q, CYSEL, G, C, K, KD + 1>(pl, s, zmask, first_lane, last_lane);
+            push_dir<Q, KD, G, C, K, NL>(pl, s, zmask, ln);
+        push_row<Q, CYSEL, G, C, K, NL, KD + 1>(pl, s, zmask, ln);
     }
 }
 
@@ -387,10 +405,15 @@ __device__ __forceinline__ int64_t uniform64(int64_t v) {
     return (int64_t)(((uint64_t)hi << 32) | lo);
 }
 
-// Chunk-table entries are read with scalar loads: the table is constant
-// while a step runs, and the row (hence the address) is wave-uniform.
+// Chunk-table entries and wall-list row offsets are read with scalar loads:
+// both tables are constant while a step runs, and the row (hence the
+// address) is wave-uniform.  A vector load whose value a scalar needs at once
+// would make the wave wait for every memory operation it has in flight --
+// the previous plane's stores included -- since loads and stores retire
+// through one in-order counter.
 typedef unsigned int ct_u4 __attribute__((ext_vector_type(4)));
 typedef const __attribute__((address_space(4))) ct_u4 ctab_t;
+typedef const __attribute__((address_space(4))) uint32_t wofs_t;
 
 // Constants of one work item (one wave).
 template <int P, int G, int C, int K>
@@ -404,13 +427,15 @@ struct ZrItem {
     rsrc_t pre[4], post[4], xm, wl;
     int abytes;
     int lane, gl;
-    bool first_lane, last_lane, active;
+    ZrLanes ln;     // lane-move facts (first / last lane, permute sources)
+    bool active;
     int nx, ny, nz, xw, z0, z1;
     int y0, yc, ym, yp;
     int voff[C];   // byte offset of the lane's chunk c inside a row
     int woff[C];   // byte offset of the lane's mask window word, chunk c
+    int wsh[C];    // bit of the chunk's first node minus one in that window
     float isr, isu, sr, su, gx, gy, gz;
-    const uint32_t* woffs;  // wall-list row offsets
+    wofs_t* woffs;          // wall-list row offsets (scalar loads)
     float* lds_res;         // bounce-back sums [4][G * nx] of this wave
     // shared-row mode (one row per wave): the workgroup's row slots
     // [2 planes][kZrWaves waves][kSlotComps components][nx], this wave's index, and
@@ -432,7 +457,7 @@ __device__ __forceinline__ void load_windows(const ZrItem<P, G, C, K>& it, int z
         const auto v = G == 1 ? __builtin_amdgcn_raw_buffer_load_b64(it.xm, it.woff[c], roff, 0)
                               : __builtin_amdgcn_raw_buffer_load_b64(it.xm, it.woff[c] + roff, 0, 0);
         const uint64_t u = ((uint64_t)v[1] << 32) | v[0];
-        win[c] = (uint32_t)(u >> ((c * (64 / G) * K + it.gl * K) & 31));
+        win[c] = (uint32_t)(u >> it.wsh[c]);
     }
 }
 
@@ -610,8 +635,8 @@ __device__ __forceinline__ void wall_offsets(const ZrItem<P, G, C, K>& it, int p
         return;
     }
     const int r0 = zc * it.ny + it.y0;
-    o0 = __builtin_amdgcn_readfirstlane((int)it.woffs[r0]);
-    o1 = __builtin_amdgcn_readfirstlane((int)it.woffs[r0 + ng]);
+    o0 = (int)it.woffs[r0];
+    o1 = (int)it.woffs[r0 + ng];
 }
 
 template <int Q>
@@ -754,7 +779,7 @@ __device__ __forceinline__ void bounce_list(const ZrItem<P, G, C, K>& it, Plane<
 // rows are read and written at their chunks' packed offsets.  Rolling
 // prefetch (mode 2, and modes 1 and 3 with G > 1): the own row of the next
 // plane (`ahead`) is requested during this plane.
-template <int Q, int P, int G, int C, int K, int MODE>
+template <int Q, int P, int G, int C, int K, int NL, int MODE>
 __device__ __forceinline__ void zr_step(const ZrItem<P, G, C, K>& it, int zs, Planes<C * K> pl,
                                         uint32_t (&win_next)[C], uint32_t& fluid_prev,
                                         WallPipe<Q>& wp, RawRow<C * K>& ahead, PkPipe<C>& pk) {
@@ -828,7 +853,7 @@ __device__ __forceinline__ void zr_step(const ZrItem<P, G, C, K>& it, int zs, Pl
 #pragma unroll
             for (int j = 0; j < PX; ++j) s[j] = make_src(ro.d[j], ro.vx[j], ro.vy[j], ro.vz[j]);
         }
-        push_row<Q, 0, G, C, K>(pl, s, zmask, it.first_lane, it.last_lane);
+        push_row<Q, 0, G, C, K, NL>(pl, s, zmask, it.ln);
         if (zmask & 2) {
             constexpr float w0 = (float)weight<Q>(0);
 #pragma unroll
@@ -864,7 +889,7 @@ __device__ __forceinline__ void zr_step(const ZrItem<P, G, C, K>& it, int zs, Pl
 #pragma unroll
             for (int j = 0; j < PX; ++j) s[j] = make_src(rm.d[j], rm.vx[j], rm.vy[j], rm.vz[j]);
         }
-        push_row<Q, 1, G, C, K>(pl, s, zmask, it.first_lane, it.last_lane);
+        push_row<Q, 1, G, C, K, NL>(pl, s, zmask, it.ln);
     }
     if constexpr (ROLL) load_row(it, wrapi((zs + 1) % nz, nz) * ny + it.yc, ahead);
     else if constexpr (!SHARE) load_row(it, rp_, rp);
@@ -876,7 +901,7 @@ __device__ __forceinline__ void zr_step(const ZrItem<P, G, C, K>& it, int zs, Pl
 #pragma unroll
             for (int j = 0; j < PX; ++j) s[j] = make_src(rp.d[j], rp.vx[j], rp.vy[j], rp.vz[j]);
         }
-        push_row<Q, -1, G, C, K>(pl, s, zmask, it.first_lane, it.last_lane);
+        push_row<Q, -1, G, C, K, NL>(pl, s, zmask, it.ln);
     }
     // ---- halfway bounce-back at this plane's wall nodes (static list)
     if (zmask & 2)
@@ -957,7 +982,7 @@ __device__ __forceinline__ void zero_plane(Plane<PX>& q) {
 // unrolled by three), so no partial sums are copied between planes.
 // The sample descriptor is read field by field with its own types and every
 // value is marked wave-uniform, so per-item quantities live in scalar registers.
-template <int Q, int P, int G, int C, int K, int MODE>
+template <int Q, int P, int G, int C, int K, int NL, int MODE>
 __device__ __forceinline__ void zr_item(const StepArgs& a, const SampleDev* sd, int rg, int z0,
                                         int z1, float* __restrict__ lds, int wave,
                                         float* __restrict__ lds_rows) {
@@ -970,8 +995,14 @@ __device__ __forceinline__ void zr_item(const StepArgs& a, const SampleDev* sd, 
     // with one row per wave the row is uniform; with G rows it depends on the lane group
     const int grp = G == 1 ? 0 : it.lane / It::Lg;
     it.gl = G == 1 ? it.lane : it.lane % It::Lg;
-    it.first_lane = it.gl == 0;
-    it.last_lane = it.gl == It::Lg - 1;
+    // lanes L..63 of a one-row layout with idle lanes hold no nodes: their
+    // offsets are out of range (no loads, no stores) and the lane moves skip
+    // them (each keeps its own value)
+    const bool idle = it.gl >= NL;
+    it.ln.first = it.gl == 0;
+    it.ln.last = it.gl == NL - 1;
+    it.ln.up = (idle ? it.gl : (it.gl == 0 ? NL - 1 : it.gl - 1)) << 2;
+    it.ln.down = (idle ? it.gl : (it.gl == NL - 1 ? 0 : it.gl + 1)) << 2;
     it.nx = __builtin_amdgcn_readfirstlane(sd->nx);
     it.ny = __builtin_amdgcn_readfirstlane(sd->ny);
     it.nz = __builtin_amdgcn_readfirstlane(sd->nz);
@@ -998,14 +1029,15 @@ __device__ __forceinline__ void zr_item(const StepArgs& a, const SampleDev* sd, 
                       (uint32_t)(((int64_t)it.xw * it.ny * it.nz + 2) * 4));
 #pragma unroll
     for (int c = 0; c < C; ++c) {
-        const int x0 = c * (It::Lg * K) + it.gl * K;
-        it.voff[c] = x0 * It::ES;
-        it.woff[c] = (x0 >> 5) * 4;
+        const int x0 = c * (NL * K) + it.gl * K;
+        it.voff[c] = idle ? kOob : x0 * It::ES;
+        it.woff[c] = idle ? 0 : (x0 >> 5) * 4;
+        it.wsh[c] = idle ? 0 : x0 & 31;
     }
     it.isr = inv_scale_rho<P>(a); it.isu = inv_scale_u<P>(a);
     it.sr = scale_rho<P>(a); it.su = scale_u<P>(a);
     it.gx = 2.0f * a.ghf[0]; it.gy = 2.0f * a.ghf[1]; it.gz = 2.0f * a.ghf[2];
-    it.woffs = reinterpret_cast<const uint32_t*>(a.base + uniform64(sd->wall_off));
+    it.woffs = (wofs_t*)(a.base + uniform64(sd->wall_off));
     it.wl = make_rsrc(a.base + uniform64(sd->wall_list),
                       (uint32_t)(uniform64(sd->n) * (int64_t)sizeof(typename WallEntry<Q>::type)));
     it.lds_res = lds;
@@ -1049,21 +1081,29 @@ __device__ __forceinline__ void zr_item(const StepArgs& a, const SampleDev* sd, 
     }
     int zs = z0 - 1;
     while (true) {
-        zr_step<Q, P, G, C, K, MODE>(it, zs, Planes<PX>{A, B, Cp}, win_next, fluid_prev, wp, rm, pk);
+        zr_step<Q, P, G, C, K, NL, MODE>(it, zs, Planes<PX>{A, B, Cp}, win_next, fluid_prev, wp, rm, pk);
         zero_plane(A);
         if (++zs > z1) break;
-        zr_step<Q, P, G, C, K, MODE>(it, zs, Planes<PX>{B, Cp, A}, win_next, fluid_prev, wp, rm, pk);
+        zr_step<Q, P, G, C, K, NL, MODE>(it, zs, Planes<PX>{B, Cp, A}, win_next, fluid_prev, wp, rm, pk);
         zero_plane(B);
         if (++zs > z1) break;
-        zr_step<Q, P, G, C, K, MODE>(it, zs, Planes<PX>{Cp, A, B}, win_next, fluid_prev, wp, rm, pk);
+        zr_step<Q, P, G, C, K, NL, MODE>(it, zs, Planes<PX>{Cp, A, B}, win_next, fluid_prev, wp, rm, pk);
         zero_plane(Cp);
         if (++zs > z1) break;
     }
 }
 
+// Occupancy target of an instance: the shared-row schedules (one row per
+// wave) and modes 1 and 3 on the multi-row layouts run at two waves per SIMD
+// (at most 256 registers per lane; the row slots of two workgroups fill a
+// CU's LDS); the other instances at one.  Modes 1/3 and 2 are the same
+// rolling-prefetch schedule on a multi-row layout, so the tile picks the
+// occupancy there.
+constexpr int zr_waves_per_simd(int g, int mode) {
+    return (zr_share(g, mode) || (g != 1 && (mode == 1 || mode == 3))) ? 2 : 1;
+}
+
 // Work item (4 x int32): sample, row group, z-segment start, z-segment end.
-// Shared-row instances target two waves per SIMD (at most 256 registers per
-// lane): the row slots of two workgroups fill a CU's LDS.
 // Workgroups are remapped so that each XCD walks a contiguous range of items
 // (neighbouring rows share their y-1 / y+1 reads in that XCD's L2).  Each
 // instance compiles one lane layout V (its register budget alone sets the
@@ -1071,10 +1111,11 @@ __device__ __forceinline__ void zr_item(const StepArgs& a, const SampleDev* sd, 
 // layout present.
 template <int Q, int P, int V, int MODE>
 __global__ __launch_bounds__(kZrThreads)
-__attribute__((amdgpu_waves_per_eu(zr_share(kVariants[V].g, MODE) ? 2 : 1)))
+__attribute__((amdgpu_waves_per_eu(zr_waves_per_simd(kVariants[V].g, MODE))))
 void k_zmarch(StepArgs a) {
     static_assert(V >= 0 && V < kNumVariants, "one lane layout per instance");
-    constexpr int G = kVariants[V].g, C = kVariants[V].c, K = kVariants[V].k;
+    constexpr int G = kVariants[V].g, C = kVariants[V].c, K = kVariants[V].k, NL = kVariants[V].l;
+    static_assert(NL == 64 / G || (G == 1 && C == 1), "idle lanes only in one-chunk, one-row layouts");
     constexpr int kPX = C * K;
     constexpr bool kShare = zr_share(G, MODE);
     // shared rows: [2 planes][kZrWaves][kSlotComps][64 * kPX] (the bounce-back
@@ -1100,10 +1141,11 @@ void k_zmarch(StepArgs a) {
     // per-item quantity (sample descriptor, buffer resources) stays scalar
     const int first = __builtin_amdgcn_readfirstlane(lb * kZrWaves + wave);
     for (int item = first; item < a.ntiles; item += nwaves) {
-        const int4 tv = reinterpret_cast<const int4*>(a.tiles)[item];
-        const int4 t = make_int4(__builtin_amdgcn_readfirstlane(tv.x), __builtin_amdgcn_readfirstlane(tv.y),
-                                 __builtin_amdgcn_readfirstlane(tv.z), __builtin_amdgcn_readfirstlane(tv.w));
-        zr_item<Q, P, G, C, K, MODE>(a, a.samples + t.x, t.y, t.z, t.w, lds_wave, wave, lds_all);
+        // the work list is constant while a step runs: a scalar load
+        typedef int wi4 __attribute__((ext_vector_type(4)));
+        typedef const __attribute__((address_space(4))) wi4 item_t;
+        const wi4 t = ((item_t*)a.tiles)[item];
+        zr_item<Q, P, G, C, K, NL, MODE>(a, a.samples + t.x, t.y, t.z, t.w, lds_wave, wave, lds_all);
     }
 }
 

@@ -16,13 +16,15 @@ namespace tau1 {
 #define TAU1_CAT(a, b, c) TAU1_CAT2(a, b, c)
 
 // Kernel of layout V for load mode 0-3; modes 1 and 3 on a multi-row layout
-// are the same schedule as mode 2 (dense layout) and use that instance.
+// are mode 2's schedule at two waves per SIMD and share one instance.
 template <int V>
 void* zm_pick(int mode) {
     if (mode == 0) return reinterpret_cast<void*>(&k_zmarch<TAU1_Q, TAU1_P, V, 0>);
     if constexpr (kVariants[V].g == 1) {
         if (mode == 1) return reinterpret_cast<void*>(&k_zmarch<TAU1_Q, TAU1_P, V, 1>);
         if (mode == 3) return reinterpret_cast<void*>(&k_zmarch<TAU1_Q, TAU1_P, V, 3>);
+    } else {
+        if (mode == 1 || mode == 3) return reinterpret_cast<void*>(&k_zmarch<TAU1_Q, TAU1_P, V, 1>);
     }
     return reinterpret_cast<void*>(&k_zmarch<TAU1_Q, TAU1_P, V, 2>);
 }

@@ -61,7 +61,8 @@ class tau1_desc(ctypes.Structure):
                 ("layout", ctypes.c_int32),
                 ("x_boundary", ctypes.c_int32),
                 ("rho_in", ctypes.c_double), ("rho_out", ctypes.c_double),
-                ("wall_u", ctypes.c_double * 3)]
+                ("wall_u", ctypes.c_double * 3),
+                ("batch_graph", ctypes.c_int32)]
 
 
 class tau1_info(ctypes.Structure):
@@ -158,7 +159,8 @@ class Sample:
 
 
 def _desc(samples, lattice, precision, g, graph_chunk, kernel, tile, f16_scales,
-          tune_cache, layout=-1, x_boundary=0, rho_in=1.0, rho_out=1.0, wall_u=(0.0, 0.0, 0.0)):
+          tune_cache, layout=-1, x_boundary=0, rho_in=1.0, rho_out=1.0, wall_u=(0.0, 0.0, 0.0),
+          batch_graph=0):
     arr = (tau1_sample * len(samples))(*[s.c_struct() for s in samples])
     d = tau1_desc()
     d.lattice = int(lattice)
@@ -179,6 +181,7 @@ def _desc(samples, lattice, precision, g, graph_chunk, kernel, tile, f16_scales,
     d.rho_out = float(rho_out)
     for a in range(3):
         d.wall_u[a] = float(wall_u[a]) if a < len(wall_u) else 0.0
+    d.batch_graph = int(batch_graph)
     return d, arr
 
 
@@ -211,7 +214,7 @@ class Sim:
     def __init__(self, samples, lattice=19, precision="f32", g=(0.0, 0.0, 0.0),
                  graph_chunk=0, kernel=-1, tile=-1, f16_scales=(0, 0),
                  tune_cache=None, device="cuda:0", layout=-1, x_boundary=0, rho_in=1.0,
-                 rho_out=1.0, wall_u=(0.0, 0.0, 0.0)):
+                 rho_out=1.0, wall_u=(0.0, 0.0, 0.0), batch_graph=0):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("Tau1 Sim needs a ROCm GPU (torch.cuda is unavailable)")
@@ -223,7 +226,8 @@ class Sim:
         self.g = tuple(float(x) for x in g)
         lib = _lib()
         d, keep = _desc(self.samples, lattice, precision, g, graph_chunk, kernel, tile,
-                        f16_scales, tune_cache, layout, x_boundary, rho_in, rho_out, wall_u)
+                        f16_scales, tune_cache, layout, x_boundary, rho_in, rho_out, wall_u,
+                        batch_graph)
         n = ctypes.c_size_t(0)
         _check(lib.tau1_workspace_size(ctypes.byref(d), ctypes.byref(n)),
                "tau1_workspace_size")

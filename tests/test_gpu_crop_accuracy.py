@@ -10,10 +10,16 @@ g = 1e-6 along x.
 - FP32 mode: rel-L2(u) and the relative permeability error within
   2000 x 2 x 2^-24 (the same linear growth of FP32 rounding as the porosity
   sweep), mass to 1e-9 relative.
-- FP16 and BF16 storage: the long-run error is printed, not pinned (the
-  short-run bounds of the parity tests hold per step; how rounding of the
-  stored state accumulates over thousands of steps has no bound derived
-  here).  The values must stay finite.
+- FP16 (default scale 2^16) and BF16 storage: every step rounds each stored
+  value once, to a relative error of at most the unit roundoff eps (2^-11,
+  2^-8).  Those errors enter the flow as independent perturbations that the
+  update carries along without amplifying them, so after n steps their sum
+  is bounded by sqrt(n) eps relative: rel-L2(u) and the relative
+  permeability error must stay within sqrt(2000) eps (2.2e-2 FP16, 0.17
+  BF16).  Mass changes only through the rounding of the stored rho - 1, at
+  most eps |rho - 1| per node and step: the relative mass drift must stay
+  within n eps mean|rho - 1| (mean over fluid nodes of the oracle's final
+  state, the largest along a run that starts from rest).
 """
 import time
 
@@ -69,3 +75,10 @@ def test_crop_2000_steps_against_oracle(crop_and_oracle, prec):
         assert e_u <= bound
         assert e_k <= bound
         assert abs(m - nf) <= 1e-9 * nf
+    else:
+        eps = 2.0 ** -11 if prec == "f16" else 2.0 ** -8
+        b_uk = np.sqrt(STEPS) * eps
+        b_m = STEPS * eps * np.abs(ref.drho[fl]).mean()
+        print(f"[bound] {prec}: rel-L2(u), k <= {b_uk:.3e}; |mass drift| <= {b_m:.3e}", flush=True)
+        assert e_u <= b_uk and e_k <= b_uk
+        assert abs(m - nf) / nf <= b_m

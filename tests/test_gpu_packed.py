@@ -14,9 +14,10 @@ from gpu_helpers import reduced_errors, run_oracle
 
 pytestmark = pytest.mark.gpu
 
-# every one-row-per-wave lane layout (nx = C * 64 * K)
+# every one-row-per-wave lane layout (nx = C * 64 * K, and the layouts with
+# idle lanes: 96 = 48 x 2, 160 = 40 x 4, 224 = 56 x 4, 288 = 48 x 6)
 G1_DIMS = [(64, 5, 7), (128, 3, 4), (192, 2, 3), (256, 3, 2), (320, 2, 2), (384, 2, 3),
-           (512, 2, 3)]
+           (512, 2, 3), (96, 5, 5), (160, 3, 3), (224, 3, 2), (288, 3, 2)]
 
 
 def state(nx, ny, nz, seed, solid_frac=0.6):

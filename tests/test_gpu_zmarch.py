@@ -19,7 +19,8 @@ def bounds(prec, u_scale):
     return {"drho_abs": (2.0 * eps + 16.0 * 2.0 ** -24) * u_scale, "u_rel_l2": 8.0 * eps}
 
 
-# nx values cover every lane layout: C chunks x (64/G) lanes x K nodes
+# nx values cover every lane layout: G rows per wave, C chunks x L lanes x K
+# nodes (L = 64 / G, or fewer: the other lanes of the wave stay idle)
 LAYOUT_DIMS = [
     (64, 5, 7),     # G=1 C=1 K=1
     (128, 3, 4),    # G=1 C=1 K=2
@@ -29,10 +30,10 @@ LAYOUT_DIMS = [
     (384, 2, 3),    # G=1 C=2 K=3
     (512, 2, 3),    # G=1 C=2 K=4
     (32, 9, 4),     # G=2 C=1 K=1
-    (96, 5, 5),     # G=2 C=1 K=3
-    (160, 3, 3),    # G=2 C=1 K=5
-    (224, 3, 2),    # G=2 C=1 K=7
-    (288, 3, 2),    # G=2 C=3 K=3
+    (96, 5, 5),     # G=1 C=1 K=2, 48 lanes
+    (160, 3, 3),    # G=1 C=1 K=4, 40 lanes
+    (224, 3, 2),    # G=1 C=1 K=4, 56 lanes
+    (288, 3, 2),    # G=1 C=1 K=6, 48 lanes
     (16, 6, 5),     # G=4 C=1 K=1
     (48, 7, 3),     # G=4 C=1 K=3
     (80, 5, 3),     # G=4 C=1 K=5
