@@ -81,11 +81,16 @@ def parse_args(argv=None):
                          "gives the headline value, all of them the median and spread")
     ap.add_argument("--sections", default="main,lattices,precision,batch,porosity,validation")
     ap.add_argument("--tile", type=int, default=-1,
-                    help="z-march tile of the main, lattices and batch sections; "
-                         "-1 = autotune")
+                    help="z-march tile of the main, lattices and batch sections and of "
+                         "the default-layout runs of the precision section; -1 = autotune")
     ap.add_argument("--graph-chunk", type=int, default=100)
     ap.add_argument("--lattice-steps", type=int, default=500)
     ap.add_argument("--precision-steps", type=int, default=2000)
+    ap.add_argument("--precision-modes", default="f32,f16,bf16",
+                    help="storage modes of the precision section")
+    ap.add_argument("--no-precision-extras", action="store_true",
+                    help="precision section: time the default layout only and skip the "
+                         "128^3 crop accuracy runs (for profiling)")
     ap.add_argument("--batch-steps", type=int, default=1000)
     ap.add_argument("--porosity-steps", type=int, default=1000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -274,11 +279,12 @@ def precision_section(gr, geo, args, out):
     import numpy as np
     from paper_2312_14742_amd import tau1
     modes = {}
-    for prec in ("f32", "f16", "bf16"):
+    precs = [p for p in args.precision_modes.split(",") if p]
+    for prec in precs:
         sim, res = gr.case([tau1.Sample(geo.solid)], 19, prec, args.precision_steps,
-                           args.warmup, args.graph_chunk, -1, label=f"precision {prec}")
+                           args.warmup, args.graph_chunk, args.tile, label=f"precision {prec}")
         sim.close()
-        if prec != "f32":
+        if prec != "f32" and not args.no_precision_extras:
             # the dense layout (tiles 0-11) beside the default packed one
             sim, rd = gr.case([tau1.Sample(geo.solid)], 19, prec, args.precision_steps,
                               args.warmup, args.graph_chunk, -1, label=f"precision {prec} dense",
@@ -286,8 +292,14 @@ def precision_section(gr, geo, args, out):
             sim.close()
             res["dense_layout"] = {k: rd[k] for k in ("gflups", "alg_gbs", "frac", "tile")}
         modes[prec] = res
-    modes["ratio_16bit_over_f32"] = {p: modes[p]["gflups"] / modes["f32"]["gflups"]
-                                     for p in ("f16", "bf16")}
+    if "f32" in modes:
+        modes["ratio_16bit_over_f32"] = {p: modes[p]["gflups"] / modes["f32"]["gflups"]
+                                         for p in ("f16", "bf16") if p in modes}
+    if args.no_precision_extras:
+        out["precision_modes"] = {
+            "workload": "D3Q19 512^3 sphere packing r=12 porosity 0.6 seed 4000, g=1e-6 x, "
+                        f"{args.precision_steps} steps per mode", "modes": modes}
+        return
     # accuracy on the 128^3 crop of the same mask (run periodic), 2000 steps
     crop = np.ascontiguousarray(geo.solid[:128, :128, :128])
     fluid = crop == 0
