@@ -108,8 +108,10 @@ typedef struct {
                                z-segment of 16/32/64/128 planes (tile % 4) x
                                load schedule (tile / 4: 0 just in time,
                                1 rows shared through LDS, 2 rolling prefetch,
-                               3 shared rows on the packed layout); a packed
-                               context takes 12-15, a dense one 0-11          */
+                               3 shared rows on the packed layout); 16 = one
+                               lane per stored chunk instead of a z-march
+                               (for rows that are mostly solid; same bits);
+                               a packed context takes 12-16, a dense one 0-11 */
     int32_t f16_log2_scale_rho; /* F16 storage: stored = value * 2^s; 0 = 16.
                                    Half holds |value| < 65504 * 2^-s (0.9995
                                    at s = 16) and is normal down to 2^-(14+s)

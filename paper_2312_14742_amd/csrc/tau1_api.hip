@@ -33,6 +33,7 @@ struct SampleHost {
     SampleDev dev;
     int64_t n_fluid;
     std::vector<uint32_t> ctab;  // packed layout: chunk table (4 words per entry)
+    int64_t nch = 0;             // packed layout: stored chunks
     std::vector<uint8_t> rowfluid;  // z-march samples: 1 if row y + ny z holds a fluid node
 };
 
@@ -139,6 +140,23 @@ int64_t chunk_table(const tau1_sample& in, int k, int groups, uint32_t* tab) {
     return rank;
 }
 
+// Chunk list of a packed sample, built on the device from its chunk table:
+// one thread per (row, group) entry writes the entries of its stored chunks.
+__global__ void k_chunk_list(const ct_u4* __restrict__ tab, uint32_t* __restrict__ list,
+                             int groups, int64_t entries) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= entries) return;
+    const ct_u4 e = tab[i];
+    uint64_t bits = ((uint64_t)e.y << 32) | e.x;
+    const uint32_t row = (uint32_t)(i / groups), g = (uint32_t)(i % groups);
+    uint32_t rank = e.z;
+    while (bits) {
+        const int l = __builtin_ctzll(bits);
+        bits &= bits - 1u;
+        list[rank++] = (row << kChunkBits) | (g * 64u + (uint32_t)l);
+    }
+}
+
 // Workspace plan; `tables` also builds the packed layout's chunk tables
 // (the size query only counts chunks).
 Plan make_plan(const tau1_desc* d, bool tables) {
@@ -172,7 +190,7 @@ Plan make_plan(const tau1_desc* d, bool tables) {
     // one-row-per-wave lane layouts only, and only where the z-march kernel
     // runs
     const bool zm = zmarch_supported(d->lattice, d->precision, p.s.data(), d->n_samples);
-    const bool auto_pack = d->precision != kF64 && (d->tile < 0 || tile_mode(d->tile) == 3);
+    const bool auto_pack = d->precision != kF64 && (d->tile < 0 || tile_packed(d->tile));
     const bool pack = zm && (d->kernel == -1 || d->kernel == 1) &&
                       (d->layout == 1 || (d->layout < 0 && auto_pack));
     // All samples of one lane layout share a launch, so a layout is packed
@@ -186,6 +204,7 @@ Plan make_plan(const tau1_desc* d, bool tables) {
         if (!layout_ok[sd.variant]) continue;
         const int k = kVariants[sd.variant].k;
         const int64_t nch = chunk_table(d->samples[i], k, kVariants[sd.variant].c, nullptr);
+        p.s[i].nch = nch;
         pstride[i] = (int64_t)(align_up((size_t)std::max<int64_t>(nch * k, 1) * sz, kAlign) / sz);
         if (4 * pstride[i] * sz + 65536 > (int64_t)kOob) layout_ok[sd.variant] = false;
     }
@@ -202,8 +221,17 @@ Plan make_plan(const tau1_desc* d, bool tables) {
         sd.stride = pstride[i];
         p.packed = true;
     }
+    for (auto& sh : p.s)
+        if (!sh.dev.pk) sh.nch = 0;  // counted, but its lane layout stays dense
     p.pack_refused = d->layout == 1 && !p.packed;
+    // work-list capacity: the longest z-march list (16-plane segments) or the
+    // chunk tile's list (one item per 64 stored chunks), whichever is longer
     tiles = zmarch_max_items(p.s.data(), d->n_samples);
+    {
+        int64_t ck = 0;
+        for (const auto& sh : p.s) ck += (sh.nch + 63) / 64;
+        tiles = std::max(tiles, ck);
+    }
     p.total_blocks = blocks;
     p.ntiles = tiles;
     p.tiles_off = off;
@@ -224,6 +252,8 @@ Plan make_plan(const tau1_desc* d, bool tables) {
         if (sd.pk) {
             sd.chunk_tab = (int64_t)off;
             off = align_up(off + 16 * (size_t)sd.ny * sd.nz * kVariants[sd.variant].c, kAlign);
+            sd.chunk_list = (int64_t)off;
+            off = align_up(off + 4 * (size_t)std::max<int64_t>(p.s[i].nch, 1), kAlign);
         }
         if (d->lattice == 9) {
             sd.types = (int64_t)off;
@@ -373,8 +403,15 @@ void* pick_d2q9(int p) {
 // per-node gather over every sample (kernel 0) or the D2Q9 kernel (2).
 Launch step_launch(const tau1_ctx* ctx, int kernel, int tile, int g) {
     Launch l{};
-    if (kernel == 1) {
+    if (kernel == 1 && tile == kChunkTile && ctx->zgroups[g].packed) {
         const auto& grp = ctx->zgroups[g];
+        l.fn = pick_chunks(ctx->lattice, ctx->precision, kVariants[grp.variant].k);
+        l.block = dim3(kCkThreads);
+        l.grid = dim3((unsigned)((grp.args[0].ntiles + kCkWaves - 1) / kCkWaves));
+        l.shmem = 0;
+    } else if (kernel == 1) {
+        const auto& grp = ctx->zgroups[g];
+        tile = tile_zmarch(tile);
         // a dense one-row layout in a packed context runs the dense shared-row schedule
         const int mode = tile_mode(tile) == 3 && !grp.packed ? 1 : tile_mode(tile);
         l.fn = pick_zmarch(ctx->lattice, ctx->precision, grp.variant, mode);
@@ -566,6 +603,13 @@ tau1_status upload_sample_t(tau1_ctx* ctx, int s, const tau1_sample& in) {
         const auto& tab = ctx->plan.s[s].ctab;
         HIP_TRY(hipMemcpyAsync(ctx->base + sd.chunk_tab, tab.data(), sizeof(uint32_t) * tab.size(),
                                hipMemcpyHostToDevice, ctx->stream));
+        // chunk list (the chunk tile's work), from the table on the device
+        const int groups = kVariants[sd.variant].c;
+        const int64_t entries = (int64_t)sd.ny * sd.nz * groups;
+        hipLaunchKernelGGL(k_chunk_list, dim3((unsigned)((entries + 255) / 256)), dim3(256), 0,
+                           ctx->stream, reinterpret_cast<const ct_u4*>(ctx->base + sd.chunk_tab),
+                           reinterpret_cast<uint32_t*>(ctx->base + sd.chunk_list), groups, entries);
+        HIP_TRY(hipGetLastError());
         HIP_TRY(hipStreamSynchronize(ctx->stream));
     }
     // state (the packed layout's upload kernel skips nodes of all-solid chunks)
@@ -695,15 +739,30 @@ tau1_status set_tile(tau1_ctx* ctx, int tile) {
     std::vector<tau1_ctx::ZGroup> groups;
     for (int v : layouts) {
         const int64_t item0 = (int64_t)tl.size() / 4;
-        std::vector<int32_t> part =
-            zmarch_worklist(ctx->plan.s.data(), ctx->nsamples, tile_lz(tile), v,
-                            zr_share(kVariants[v].g, tile_mode(tile)));
-        tl.insert(tl.end(), part.begin(), part.end());
         tau1_ctx::ZGroup g;
         g.variant = v;
         g.packed = false;
         for (const auto& sh : ctx->plan.s)
             if (sh.dev.variant == v && sh.dev.pk) g.packed = true;
+        if (tile == kChunkTile && g.packed) {
+            // the chunk kernel: one item per 64 stored chunks of a sample
+            for (int i = 0; i < ctx->nsamples; ++i) {
+                const auto& sh = ctx->plan.s[i];
+                if (sh.dev.variant != v) continue;
+                for (int64_t c0 = 0; c0 < sh.nch; c0 += 64) {
+                    tl.push_back(i);
+                    tl.push_back((int32_t)c0);
+                    tl.push_back((int32_t)std::min<int64_t>(64, sh.nch - c0));
+                    tl.push_back(0);
+                }
+            }
+        } else {
+            const int zt = tile_zmarch(tile);
+            std::vector<int32_t> part =
+                zmarch_worklist(ctx->plan.s.data(), ctx->nsamples, tile_lz(zt), v,
+                                zr_share(kVariants[v].g, tile_mode(zt)));
+            tl.insert(tl.end(), part.begin(), part.end());
+        }
         for (int p = 0; p < 2; ++p) {
             g.args[p] = ctx->args[p];
             g.args[p].tiles = reinterpret_cast<const int32_t*>(ctx->base + ctx->plan.tiles_off) +

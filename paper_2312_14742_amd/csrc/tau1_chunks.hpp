@@ -1,0 +1,265 @@
+// tau1_chunks.hpp -- step kernel over the stored chunks of the packed layout.
+//
+// In a porous medium of low porosity most lane chunks of a row are solid, yet
+// the z-march evaluates every node of every row segment that holds fluid.
+// This kernel's work follows the stored chunks instead: one lane per chunk of
+// the packed layout (K consecutive x-nodes holding at least one fluid node),
+// 64 consecutive chunks of one sample per wave, in storage order, so the
+// lane's own chunk is read and written with coalesced vector accesses.
+//
+// For each of its K nodes the lane gathers the equilibria of Eq. (3) that the
+// neighbours send it (the pull form of Eqs. (9)-(10)): it reads the nine
+// (y, z) neighbour columns of its chunk -- the chunk at the same x-position
+// in each neighbour row, plus the node on either side in x where a direction
+// needs it -- through the chunk table, so an all-solid chunk reads as zeros,
+// which a solid node sends anyway.  Halfway bounce-back (Eq. 11) returns the
+// node's own equilibria along its solid links, which come from the extended
+// solid mask of the same nine rows.
+//
+// Every destination sum is formed in the order in which the z-march forms
+// it: source plane z-1, then z, then z+1; within a plane the own row, then
+// row y-1, then row y+1; within a row the lattice directions in order; the
+// rest population after the own row of plane z and the wall returns after
+// row y+1 of plane z.  Both kernels therefore give the same bits, and the
+// autotuner may pick either.
+#pragma once
+
+#include "tau1_zmarch.hpp"
+
+namespace tau1 {
+
+template <int Q, int CY, int CZ, int KD = 1>
+constexpr bool ck_has_dir() {
+    if constexpr (KD >= Q) {
+        return false;
+    } else {
+        using L = Lattice<Q>;
+        return (L::c[KD].y == CY && L::c[KD].z == CZ) || ck_has_dir<Q, CY, CZ, KD + 1>();
+    }
+}
+
+// Whether some direction of the column (c_y, c_z) = (CY, CZ) has c_x != 0:
+// its sources then include the nodes on either side of the chunk.
+template <int Q, int CY, int CZ, int KD = 1>
+constexpr bool ck_needs_edges() {
+    if constexpr (KD >= Q) {
+        return false;
+    } else {
+        using L = Lattice<Q>;
+        return (L::c[KD].y == CY && L::c[KD].z == CZ && L::c[KD].x != 0) ||
+               ck_needs_edges<Q, CY, CZ, KD + 1>();
+    }
+}
+
+struct CkCtx {
+    rsrc_t pre, post;                 // the read and the written buffer (four arrays each)
+    int abytes;                       // bytes per array
+    const ct_u4* tab;                 // chunk table of the sample
+    const uint32_t* xm;               // extended solid mask
+    int nx, ny, nz, xw, groups, nch;  // nch: chunks per row
+    float isr, isu;
+};
+
+// Byte offset of chunk cj of row `row` in a state array, or the out-of-range
+// offset when the chunk is not stored (all solid).
+template <int K, int ES>
+__device__ __forceinline__ int ck_offset(const CkCtx& c, int row, int cj) {
+    const ct_u4 e = c.tab[(int64_t)row * c.groups + (cj >> 6)];
+    const uint64_t bits = ((uint64_t)e.y << 32) | e.x;
+    const int l = cj & 63;
+    const uint64_t below = bits & ((uint64_t(1) << l) - 1u);
+    return ((bits >> l) & 1u) ? (int)((e.z + (uint32_t)__popcll(below)) * (uint32_t)(K * ES)) : kOob;
+}
+
+// Source terms of the column's nodes x0 - 1 .. x0 + K (slots 0 .. K + 1); the
+// two edge slots only where a direction of the column needs them.
+template <int P, int K, bool EDGES>
+__device__ __forceinline__ void ck_column(const CkCtx& c, int row, int ci, Src (&s)[K + 2]) {
+    constexpr int ES = (int)sizeof(typename Storage<P>::S);
+    const int vo = ck_offset<K, ES>(c, row, ci);
+    float d[K], vx[K], vy[K], vz[K];
+    load_chunk<P, K>(c.pre, vo, 0, d, c.isr);
+    load_chunk<P, K>(c.pre, vo, c.abytes, vx, c.isu);
+    load_chunk<P, K>(c.pre, vo, 2 * c.abytes, vy, c.isu);
+    load_chunk<P, K>(c.pre, vo, 3 * c.abytes, vz, c.isu);
+#pragma unroll
+    for (int j = 0; j < K; ++j) s[j + 1] = make_src(d[j], vx[j], vy[j], vz[j]);
+    if constexpr (EDGES) {
+        // last node of the chunk before, first node of the chunk after (periodic in x)
+        const int cl = ci == 0 ? c.nch - 1 : ci - 1;
+        const int cr = ci == c.nch - 1 ? 0 : ci + 1;
+        int ol = ck_offset<K, ES>(c, row, cl);
+        const int orr = ck_offset<K, ES>(c, row, cr);
+        ol = ol == kOob ? kOob : ol + (K - 1) * ES;
+        float e[2][4];
+        e[0][0] = load_one<P>(c.pre, ol, 0, c.isr);
+        e[1][0] = load_one<P>(c.pre, orr, 0, c.isr);
+#pragma unroll
+        for (int a = 1; a < 4; ++a) {
+            e[0][a] = load_one<P>(c.pre, ol, a * c.abytes, c.isu);
+            e[1][a] = load_one<P>(c.pre, orr, a * c.abytes, c.isu);
+        }
+        s[0] = make_src(e[0][0], e[0][1], e[0][2], e[0][3]);
+        s[K + 1] = make_src(e[1][0], e[1][1], e[1][2], e[1][3]);
+    }
+}
+
+// Adds the contributions of one source column: every direction k with
+// (c_y, c_z) = (CY, CZ), in order, from source node x - c_x to node x.  The
+// multiply-adds are those of the z-march's push (add_to).
+template <int Q, int CY, int CZ, int K, int KD = 1>
+__device__ __forceinline__ void ck_pull(float (&acc)[4][K], const Src (&s)[K + 2]) {
+    if constexpr (KD < Q) {
+        using L = Lattice<Q>;
+        constexpr int CX = L::c[KD].x;
+        if constexpr (L::c[KD].y == CY && L::c[KD].z == CZ) {
+            constexpr float w = (float)weight<Q>(KD);
+#pragma unroll
+            for (int j = 0; j < K; ++j) {
+                const float u = feq_m<CX, CY, CZ>(s[j + 1 - CX]);
+                acc[0][j] = __builtin_fmaf(w, u, acc[0][j]);
+                if constexpr (CX != 0) acc[1][j] = __builtin_fmaf(CX * w, u, acc[1][j]);
+                if constexpr (CY != 0) acc[2][j] = __builtin_fmaf(CY * w, u, acc[2][j]);
+                if constexpr (CZ != 0) acc[3][j] = __builtin_fmaf(CZ * w, u, acc[3][j]);
+            }
+        }
+        ck_pull<Q, CY, CZ, K, KD + 1>(acc, s);
+    }
+}
+
+// Source column (source row offset -CY, plane offset -CZ from the node): its
+// directions c_y = CY, c_z = CZ.
+template <int Q, int P, int CY, int CZ, int K>
+__device__ __forceinline__ void ck_source(const CkCtx& c, int y, int z, int ci,
+                                          float (&acc)[4][K]) {
+    if constexpr (ck_has_dir<Q, CY, CZ>()) {
+        const int row = wrapi(z - CZ, c.nz) * c.ny + wrapi(y - CY, c.ny);
+        Src s[K + 2];
+        ck_column<P, K, ck_needs_edges<Q, CY, CZ>()>(c, row, ci, s);
+        ck_pull<Q, CY, CZ, K>(acc, s);
+    }
+}
+
+// Solid links of node j (bit k - 1: neighbour x + c_k is solid) from the
+// nine mask windows win[CY + 1][CZ + 1], whose bit b is node x0 - 1 + b.
+template <int Q, int KD = 1>
+__device__ __forceinline__ uint32_t ck_links(const uint32_t (&win)[3][3], int j) {
+    if constexpr (KD >= Q) {
+        return 0u;
+    } else {
+        using L = Lattice<Q>;
+        constexpr int CX = L::c[KD].x, CY = L::c[KD].y, CZ = L::c[KD].z;
+        const uint32_t b = (win[CY + 1][CZ + 1] >> (j + 1 + CX)) & 1u;
+        return (b << (KD - 1)) | ck_links<Q, KD + 1>(win, j);
+    }
+}
+
+template <int Q, int P, int K>
+__global__ __launch_bounds__(kCkThreads) void k_chunks(StepArgs a) {
+    using St = Storage<P>;
+    constexpr int ES = (int)sizeof(typename St::S);
+    const int wave = threadIdx.x >> 6;
+    const int item = __builtin_amdgcn_readfirstlane(blockIdx.x * kCkWaves + wave);
+    if (item >= a.ntiles) return;
+    typedef int wi4 __attribute__((ext_vector_type(4)));
+    typedef const __attribute__((address_space(4))) wi4 item_t;
+    const wi4 t = ((item_t*)a.tiles)[item];
+    const int lane = __lane_id();
+    if (lane >= t.z) return;
+    const SampleDev* sd = a.samples + t.x;
+
+    CkCtx c;
+    c.nx = __builtin_amdgcn_readfirstlane(sd->nx);
+    c.ny = __builtin_amdgcn_readfirstlane(sd->ny);
+    c.nz = __builtin_amdgcn_readfirstlane(sd->nz);
+    c.xw = __builtin_amdgcn_readfirstlane(sd->xwords);
+    c.nch = c.nx / K;
+    c.groups = (c.nch + 63) / 64;
+    const int64_t stride = uniform64(sd->stride);
+    c.abytes = (int)(uint32_t)(stride * ES);
+    const int64_t st0 = uniform64(sd->state[0]), st1 = uniform64(sd->state[1]);
+    c.pre = make_rsrc(a.base + (a.parity ? st1 : st0), 4u * (uint32_t)c.abytes);
+    c.post = make_rsrc(a.base + (a.parity ? st0 : st1), 4u * (uint32_t)c.abytes);
+    c.tab = reinterpret_cast<const ct_u4*>(a.base + uniform64(sd->chunk_tab));
+    c.xm = reinterpret_cast<const uint32_t*>(a.base + uniform64(sd->xmask));
+    c.isr = inv_scale_rho<P>(a);
+    c.isu = inv_scale_u<P>(a);
+
+    const int p = t.y + lane;  // packed index of the lane's chunk
+    const uint32_t e = reinterpret_cast<const uint32_t*>(a.base + uniform64(sd->chunk_list))[p];
+    const int row = (int)(e >> kChunkBits), ci = (int)(e & ((1u << kChunkBits) - 1u));
+    const int y = row % c.ny, z = row / c.ny;
+    const int x0 = ci * K;
+
+    // solid windows of the nine neighbour rows: bit b is node x0 - 1 + b
+    uint32_t win[3][3];
+#pragma unroll
+    for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+        for (int dz = -1; dz <= 1; ++dz)
+            win[dy + 1][dz + 1] = xmask_window(
+                c.xm, (int64_t)wrapi(z + dz, c.nz) * c.ny + wrapi(y + dy, c.ny), c.xw, x0);
+
+    float acc[4][K];
+#pragma unroll
+    for (int comp = 0; comp < 4; ++comp)
+#pragma unroll
+        for (int j = 0; j < K; ++j) acc[comp][j] = 0.0f;
+
+    // source plane z - 1 (directions with c_z = +1): own row, row y-1, row y+1
+    ck_source<Q, P, 0, 1, K>(c, y, z, ci, acc);
+    ck_source<Q, P, 1, 1, K>(c, y, z, ci, acc);
+    ck_source<Q, P, -1, 1, K>(c, y, z, ci, acc);
+    // source plane z: own row (c_y = c_z = 0), the rest population, rows y-1, y+1
+    Src own[K + 2];
+    ck_column<P, K, true>(c, row, ci, own);
+    ck_pull<Q, 0, 0, K>(acc, own);
+    {
+        constexpr float w0 = (float)weight<Q>(0);
+#pragma unroll
+        for (int j = 0; j < K; ++j) acc[0][j] = __builtin_fmaf(w0, own[j + 1].a, acc[0][j]);
+    }
+    ck_source<Q, P, 1, 0, K>(c, y, z, ci, acc);
+    ck_source<Q, P, -1, 0, K>(c, y, z, ci, acc);
+    // wall returns of the fluid nodes with a solid link (for the others the
+    // z-march adds zeros, which leaves the sums as they are)
+    uint32_t fluid = 0;
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        const bool f = !((win[1][1] >> (j + 1)) & 1u);
+        fluid |= (uint32_t)f << j;
+        const uint32_t links = ck_links<Q>(win, j);
+        if (f && links != 0u) {
+            float r[4];
+            wall_sums<Q>(own[j + 1], links, r);
+#pragma unroll
+            for (int comp = 0; comp < 4; ++comp) acc[comp][j] += r[comp];
+        }
+    }
+    // source plane z + 1 (directions with c_z = -1)
+    ck_source<Q, P, 0, -1, K>(c, y, z, ci, acc);
+    ck_source<Q, P, 1, -1, K>(c, y, z, ci, acc);
+    ck_source<Q, P, -1, -1, K>(c, y, z, ci, acc);
+
+    // finalise (as the z-march) and store the chunk, solid slots as zeros
+    const float gx = 2.0f * a.ghf[0], gy = 2.0f * a.ghf[1], gz = 2.0f * a.ghf[2];
+    float od[K], ox[K], oy[K], oz[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        const bool f = (fluid >> j) & 1u;
+        const float d = acc[0][j];
+        const float r = __builtin_amdgcn_rcpf(1.0f + d);
+        od[j] = f ? d : 0.0f;
+        ox[j] = f ? __builtin_fmaf(acc[1][j], r, gx) : 0.0f;
+        oy[j] = f ? __builtin_fmaf(acc[2][j], r, gy) : 0.0f;
+        oz[j] = f ? __builtin_fmaf(acc[3][j], r, gz) : 0.0f;
+    }
+    const float sr = scale_rho<P>(a), su = scale_u<P>(a);
+    const uint32_t vo = (uint32_t)p * (uint32_t)(K * ES), ab = (uint32_t)c.abytes;
+    store_chunk<P, K>(c.post, (int)vo, 0, od, sr);
+    store_chunk<P, K>(c.post, (int)(vo + ab), 0, ox, su);
+    store_chunk<P, K>(c.post, (int)(vo + 2 * ab), 0, oy, su);
+    store_chunk<P, K>(c.post, (int)(vo + 3 * ab), 0, oz, su);
+}
+
+}  // namespace tau1

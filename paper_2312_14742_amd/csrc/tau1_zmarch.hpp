@@ -65,10 +65,23 @@ constexpr int kZrThreads = 64 * kZrWaves;
 //   3  as 1, for samples stored in the packed layout (only all-solid lane
 //      chunks are left out of memory); the tiles of a context are those of
 //      its layout: 0-2 dense, 3 packed.
-constexpr int kNumTiles = 16;
+// Tile 16 (packed layout only) is not a z-march: one lane per stored chunk
+// (k_chunks), for media whose rows are mostly solid; it gives the same bits.
+constexpr int kChunkTile = 16;
+constexpr int kNumTiles = 17;
 constexpr int kTileLZ[4] = {16, 32, 64, 128};
 inline int tile_lz(int tile) { return kTileLZ[tile & 3]; }
 inline int tile_mode(int tile) { return tile / 4; }
+// Chunk tile: its work item (4 x int32) is sample, first packed chunk,
+// number of chunks (at most 64, one wave), unused; its chunk list entry holds
+// row y + ny z (bits 7..31) and chunk index in the row (bits 0..6).
+constexpr int kCkWaves = 4;
+constexpr int kCkThreads = 64 * kCkWaves;
+constexpr int kChunkBits = 7;
+inline bool tile_packed(int tile) { return tile_mode(tile) == 3 || tile == kChunkTile; }
+// The z-march tile that stands in for the chunk tile in a launch group that
+// is not packed (a batch may mix packed and dense lane layouts).
+inline int tile_zmarch(int tile) { return tile == kChunkTile ? 14 : tile; }
 
 // Load schedule of a (layout, mode) pair: shared rows need one row per wave.
 constexpr bool zr_share(int g, int mode) { return (mode == 1 || mode == 3) && g == 1; }
@@ -392,6 +405,21 @@ __device__ __forceinline__ void bounce_sum(const Src& s, uint32_t links, float (
         if constexpr (CZ != 0) j[cls][2] -= CZ * u;
         bounce_sum<Q, KD + 1>(s, links, d, j);
     }
+}
+
+// Weighted wall returns of one node: density and momentum (r[0], r[1..3]) of
+// the populations its solid links send back.  The step kernels all add these
+// four values to the node's sums at the same point, so they share this code.
+template <int Q>
+__device__ __forceinline__ void wall_sums(const Src& sw, uint32_t links, float (&r)[4]) {
+    float sd[3] = {0.f, 0.f, 0.f};
+    float sj[3][3] = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};
+    bounce_sum<Q>(sw, links, sd, sj);
+    constexpr float wf = (float)Lattice<Q>::w_face, we = (float)Lattice<Q>::w_edge,
+                    wc = (float)Lattice<Q>::w_corner;
+    r[0] = wf * sd[0] + we * sd[1] + wc * sd[2];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) r[1 + a] = wf * sj[0][a] + we * sj[1][a] + wc * sj[2][a];
 }
 
 __device__ __forceinline__ int wrapi(int a, int n) {
@@ -739,14 +767,10 @@ __device__ __forceinline__ void bounce_list(const ZrItem<P, G, C, K>& it, Plane<
             } else {
                 sw = make_src(v[0], v[1], v[2], v[3]);
             }
-            float sd[3] = {0.f, 0.f, 0.f};
-            float sj[3][3] = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};
-            bounce_sum<Q>(sw, links, sd, sj);
-            constexpr float wf = (float)Lattice<Q>::w_face, we = (float)Lattice<Q>::w_edge,
-                            wc = (float)Lattice<Q>::w_corner;
-            res[n] = wf * sd[0] + we * sd[1] + wc * sd[2];
+            float r[4];
+            wall_sums<Q>(sw, links, r);
 #pragma unroll
-            for (int a = 0; a < 3; ++a) res[(1 + a) * RS + n] = wf * sj[0][a] + we * sj[1][a] + wc * sj[2][a];
+            for (int c = 0; c < 4; ++c) res[c * RS + n] = r[c];
         }
     }
     __builtin_amdgcn_wave_barrier();
@@ -1151,7 +1175,8 @@ void k_zmarch(StepArgs a) {
 
 // Kernel table of one (lattice, precision) pair; defined in the per-pair
 // translation units built from tau1_zmarch_inst.hip.
-#define TAU1_ZM_TABLE_DECL(QQ, PP) void* zm_kernel_##QQ##_##PP(int variant, int mode);
+#define TAU1_ZM_TABLE_DECL(QQ, PP) \
+    void* zm_kernel_##QQ##_##PP(int variant, int mode); void* ck_kernel_##QQ##_##PP(int k);
 TAU1_ZM_TABLE_DECL(15, 1) TAU1_ZM_TABLE_DECL(15, 2) TAU1_ZM_TABLE_DECL(15, 3)
 TAU1_ZM_TABLE_DECL(19, 1) TAU1_ZM_TABLE_DECL(19, 2) TAU1_ZM_TABLE_DECL(19, 3)
 TAU1_ZM_TABLE_DECL(27, 1) TAU1_ZM_TABLE_DECL(27, 2) TAU1_ZM_TABLE_DECL(27, 3)
@@ -1164,10 +1189,11 @@ inline int zr_xwords(int nx) { return (nx + 2 + 31) / 32 + 1; }
 
 inline bool zmarch_precision_ok(int prec) { return prec == kF32 || prec == kF16 || prec == kBF16; }
 
-// Tiles of a context: mode 3 exactly when its samples use the packed layout.
+// Tiles of a context: modes 0-2 on the dense layout, mode 3 and the chunk
+// tile on the packed layout.
 inline bool zmarch_tile_ok(int prec, bool packed, int tile) {
     return zmarch_precision_ok(prec) && tile >= 0 && tile < kNumTiles &&
-           (tile_mode(tile) == 3) == packed;
+           tile_packed(tile) == packed;
 }
 
 // z-segments of 64 planes
@@ -1184,6 +1210,21 @@ inline void* pick_zmarch(int q, int p, int variant, int mode) {
         case 271: return zm_kernel_27_1(variant, mode);
         case 272: return zm_kernel_27_2(variant, mode);
         case 273: return zm_kernel_27_3(variant, mode);
+    }
+    return nullptr;
+}
+
+inline void* pick_chunks(int q, int p, int k) {
+    switch (q * 10 + p) {
+        case 151: return ck_kernel_15_1(k);
+        case 152: return ck_kernel_15_2(k);
+        case 153: return ck_kernel_15_3(k);
+        case 191: return ck_kernel_19_1(k);
+        case 192: return ck_kernel_19_2(k);
+        case 193: return ck_kernel_19_3(k);
+        case 271: return ck_kernel_27_1(k);
+        case 272: return ck_kernel_27_2(k);
+        case 273: return ck_kernel_27_3(k);
     }
     return nullptr;
 }

@@ -9,7 +9,8 @@ import pytest
 from paper_2312_14742_amd import inputs, tau1
 
 # one-row-per-wave lane layouts: nx -> (chunk length K, groups of 64 chunks per row)
-G1 = {64: (1, 1), 128: (2, 1), 192: (3, 1), 256: (4, 1), 320: (5, 1), 384: (3, 2), 512: (4, 2)}
+G1 = {64: (1, 1), 128: (2, 1), 192: (3, 1), 256: (4, 1), 320: (5, 1), 384: (3, 2), 512: (4, 2),
+      96: (2, 1), 160: (4, 1), 224: (4, 1), 288: (6, 1)}
 
 
 @pytest.fixture(scope="module")
@@ -26,6 +27,28 @@ def fluid_chunks(solid, k):
     return int(np.any(solid.reshape(nz, ny, nx // k, k) == 0, axis=-1).sum())
 
 
+def zmarch_items(solids):
+    """Longest z-march work list: rows padded to blocks of four, 16-plane segments."""
+    return sum((s.shape[1] + 3) // 4 * 4 * ((s.shape[0] + 15) // 16) for s in solids)
+
+
+def packed_extra(solids, packed):
+    """Workspace the packed layout adds besides its smaller state buffers: per
+    packed sample the chunk table (16 B per row and group) and the chunk list
+    (4 B per stored chunk), and a work list long enough for the chunk tile
+    (one 16-B item per 64 stored chunks of each packed sample)."""
+    extra = 0
+    waves = 0
+    for s in packed:
+        nz, ny, nx = s.shape
+        k, groups = G1[nx]
+        nch = fluid_chunks(s, k)
+        extra += align(16 * ny * nz * groups) + align(4 * max(nch, 1))
+        waves += (nch + 63) // 64
+    items = zmarch_items(solids)
+    return extra + align(16 * max(items, waves, 1)) - align(16 * max(items, 1))
+
+
 @pytest.mark.parametrize("prec,es", [("f32", 4), ("f16", 2), ("bf16", 2)])
 @pytest.mark.parametrize("nx", sorted(G1))
 def test_packed_workspace_holds_fluid_chunks(lib, nx, prec, es):
@@ -37,19 +60,24 @@ def test_packed_workspace_holds_fluid_chunks(lib, nx, prec, es):
     n = nx * ny * nz
     ds = align(n * es) // es
     ps = align(max(fluid_chunks(solid, k) * k, 1) * es) // es
-    # two buffers of four arrays each, plus the chunk table (16 B per row and group)
-    expect = dense - 2 * (align(4 * ds * es) - align(4 * ps * es)) + align(16 * ny * nz * groups)
+    # two buffers of four arrays each, plus the chunk table and list
+    expect = dense - 2 * (align(4 * ds * es) - align(4 * ps * es)) + packed_extra([solid], [solid])
     assert packed == expect
 
 
-def test_packed_is_default_for_f32_only(lib):
+def test_packed_is_default_for_zmarch_precisions(lib):
     solid = inputs.random_state(256, 3, 5, seed=9100, solid_frac=0.7)[0]
-    for prec in ("f32", "f16"):
+    for prec in ("f32", "f16", "bf16"):
         auto = tau1.workspace_size([(solid,)], precision=prec)
         dense = tau1.workspace_size([(solid,)], precision=prec, layout=0)
         packed = tau1.workspace_size([(solid,)], precision=prec, layout=1)
         assert packed < dense
-        assert auto == (packed if prec == "f32" else dense)
+        assert auto == packed
+    # FP64 runs the per-node gather on the dense layout
+    assert tau1.workspace_size([(solid,)], precision="f64") == \
+        tau1.workspace_size([(solid,)], precision="f64", layout=0)
+    # the chunk tile belongs to the packed layout
+    assert tau1.workspace_size([(solid,)], tile=16) == tau1.workspace_size([(solid,)], layout=1)
     # a dense-layout tile keeps the automatic layout dense
     assert tau1.workspace_size([(solid,)], tile=6) == tau1.workspace_size([(solid,)], layout=0)
     assert tau1.workspace_size([(solid,)], tile=14) == tau1.workspace_size([(solid,)], layout=1)
@@ -63,15 +91,15 @@ def test_all_solid_and_all_fluid_samples(lib):
     p_solid = tau1.workspace_size([(solid,)], layout=1)
     d_fluid = tau1.workspace_size([(fluid,)], layout=0)
     p_fluid = tau1.workspace_size([(fluid,)], layout=1)
-    table = align(16 * ny * nz * 2)
-    assert p_fluid == d_fluid + table
-    assert p_solid == d_solid - 2 * (align(4 * 512 * ny * nz * 4) - align(4 * 64 * 4)) + table
+    assert p_fluid == d_fluid + packed_extra([fluid], [fluid])
+    assert p_solid == (d_solid - 2 * (align(4 * 512 * ny * nz * 4) - align(4 * 64 * 4)) +
+                       packed_extra([solid], [solid]))
 
 
 @pytest.mark.parametrize("kw", [
     dict(precision="f64"),                 # the FP64 path is the per-node gather
     dict(kernel=0),                        # the gather kernel reads the dense layout
-    dict(nx=96),                           # two rows per wave: no packed kernel
+    dict(nx=32),                           # two rows per wave: no packed kernel
     dict(nx=100),                          # no z-march lane layout at all
 ])
 def test_packed_refused(lib, kw):
@@ -110,4 +138,5 @@ def test_oversized_layout_stays_dense(lib):
     k, groups = G1[256]
     ds = align(other.size * 4) // 4
     ps = align(fluid_chunks(other, k) * k * 4) // 4
-    assert packed == dense - 2 * (align(4 * ds * 4) - align(4 * ps * 4)) + align(16 * 6 * 5 * groups)
+    assert packed == (dense - 2 * (align(4 * ds * 4) - align(4 * ps * 4)) +
+                      packed_extra([big, small, other], [other]))
