@@ -60,44 +60,87 @@ struct CkCtx {
     float isr, isu;
 };
 
-// Byte offset of chunk cj of row `row` in a state array, or the out-of-range
-// offset when the chunk is not stored (all solid).
+// Byte offset of the chunk with bit l of table entry e (K-node chunks of ES
+// bytes per value), or the out-of-range offset when the chunk is not stored.
 template <int K, int ES>
-__device__ __forceinline__ int ck_offset(const CkCtx& c, int row, int cj) {
-    const ct_u4 e = c.tab[(int64_t)row * c.groups + (cj >> 6)];
+__device__ __forceinline__ int ck_slot(const ct_u4& e, int l) {
     const uint64_t bits = ((uint64_t)e.y << 32) | e.x;
-    const int l = cj & 63;
     const uint64_t below = bits & ((uint64_t(1) << l) - 1u);
     return ((bits >> l) & 1u) ? (int)((e.z + (uint32_t)__popcll(below)) * (uint32_t)(K * ES)) : kOob;
 }
 
+// Byte offset of chunk cj of row `row` in a state array (or out of range).
+template <int K, int ES>
+__device__ __forceinline__ int ck_offset(const CkCtx& c, int row, int cj) {
+    return ck_slot<K, ES>(c.tab[(int64_t)row * c.groups + (cj >> 6)], cj & 63);
+}
+
+// Lane moves across the whole wave: from lane l - 1 (ror) and from lane l + 1 (rol).
+__device__ __forceinline__ float ck_from_prev(float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(
+        0, __builtin_bit_cast(int, v), 0x13C, 0xf, 0xf, false));  // wave_ror:1
+}
+__device__ __forceinline__ float ck_from_next(float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(
+        0, __builtin_bit_cast(int, v), 0x134, 0xf, 0xf, false));  // wave_rol:1
+}
+
+// Where a lane's x-neighbour chunks are: the lanes before and after it hold
+// the chunks ci - 1 and ci + 1 of the same row when those are stored (the
+// list is in storage order); otherwise the edge node is read from memory.
+struct CkNb {
+    bool left, right;  // lane l - 1 / l + 1 holds chunk ci - 1 / ci + 1 of this row
+    int cl, cr;        // the neighbour chunk indices (periodic in x)
+};
+
 // Source terms of the column's nodes x0 - 1 .. x0 + K (slots 0 .. K + 1); the
-// two edge slots only where a direction of the column needs them.
+// two edge slots only where a direction of the column needs them.  Every
+// lane of the wave takes part (the edge values move between lanes).  All
+// loads of a column depend only on its table entries, so they are in flight
+// together: the edge reads of lanes whose neighbour lane holds the edge use
+// an out-of-range offset (no memory access) instead of a branch.
 template <int P, int K, bool EDGES>
-__device__ __forceinline__ void ck_column(const CkCtx& c, int row, int ci, Src (&s)[K + 2]) {
+__device__ __forceinline__ void ck_column(const CkCtx& c, int row, int ci, const CkNb& nb,
+                                          Src (&s)[K + 2]) {
     constexpr int ES = (int)sizeof(typename Storage<P>::S);
-    const int vo = ck_offset<K, ES>(c, row, ci);
-    float d[K], vx[K], vy[K], vz[K];
-    load_chunk<P, K>(c.pre, vo, 0, d, c.isr);
-    load_chunk<P, K>(c.pre, vo, c.abytes, vx, c.isu);
-    load_chunk<P, K>(c.pre, vo, 2 * c.abytes, vy, c.isu);
-    load_chunk<P, K>(c.pre, vo, 3 * c.abytes, vz, c.isu);
-#pragma unroll
-    for (int j = 0; j < K; ++j) s[j + 1] = make_src(d[j], vx[j], vy[j], vz[j]);
+    // the row's table entry of the chunk's group, and of the other group
+    // (the same entry when a row has one group); a row has at most two
+    const int64_t rb = (int64_t)row * c.groups;
+    const int g = ci >> 6;
+    const ct_u4 te = c.tab[rb + g];
+    const int vo = ck_slot<K, ES>(te, ci & 63);
+    float v[4][K];
+    load_chunk<P, K>(c.pre, vo, 0, v[0], c.isr);
+    load_chunk<P, K>(c.pre, vo, c.abytes, v[1], c.isu);
+    load_chunk<P, K>(c.pre, vo, 2 * c.abytes, v[2], c.isu);
+    load_chunk<P, K>(c.pre, vo, 3 * c.abytes, v[3], c.isu);
+    float e[2][4];
     if constexpr (EDGES) {
-        // last node of the chunk before, first node of the chunk after (periodic in x)
-        const int cl = ci == 0 ? c.nch - 1 : ci - 1;
-        const int cr = ci == c.nch - 1 ? 0 : ci + 1;
-        int ol = ck_offset<K, ES>(c, row, cl);
-        const int orr = ck_offset<K, ES>(c, row, cr);
-        ol = ol == kOob ? kOob : ol + (K - 1) * ES;
-        float e[2][4];
+        const ct_u4 to = c.tab[rb + (g ^ (c.groups - 1))];
+        int ol = ck_slot<K, ES>((nb.cl >> 6) == g ? te : to, nb.cl & 63);
+        ol = (nb.left || ol == kOob) ? kOob : ol + (K - 1) * ES;
+        int orr = ck_slot<K, ES>((nb.cr >> 6) == g ? te : to, nb.cr & 63);
+        orr = nb.right ? kOob : orr;
         e[0][0] = load_one<P>(c.pre, ol, 0, c.isr);
         e[1][0] = load_one<P>(c.pre, orr, 0, c.isr);
 #pragma unroll
         for (int a = 1; a < 4; ++a) {
             e[0][a] = load_one<P>(c.pre, ol, a * c.abytes, c.isu);
             e[1][a] = load_one<P>(c.pre, orr, a * c.abytes, c.isu);
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < K; ++j) s[j + 1] = make_src(v[0][j], v[1][j], v[2][j], v[3][j]);
+    if constexpr (EDGES) {
+        // last node of the chunk before, first node of the chunk after: from
+        // the neighbouring lanes' loads of this column where they hold those
+        // chunks
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+            const float pv = ck_from_prev(v[a][K - 1]);
+            const float nv = ck_from_next(v[a][0]);
+            e[0][a] = nb.left ? pv : e[0][a];
+            e[1][a] = nb.right ? nv : e[1][a];
         }
         s[0] = make_src(e[0][0], e[0][1], e[0][2], e[0][3]);
         s[K + 1] = make_src(e[1][0], e[1][1], e[1][2], e[1][3]);
@@ -130,12 +173,12 @@ __device__ __forceinline__ void ck_pull(float (&acc)[4][K], const Src (&s)[K + 2
 // Source column (source row offset -CY, plane offset -CZ from the node): its
 // directions c_y = CY, c_z = CZ.
 template <int Q, int P, int CY, int CZ, int K>
-__device__ __forceinline__ void ck_source(const CkCtx& c, int y, int z, int ci,
+__device__ __forceinline__ void ck_source(const CkCtx& c, int y, int z, int ci, const CkNb& nb,
                                           float (&acc)[4][K]) {
     if constexpr (ck_has_dir<Q, CY, CZ>()) {
         const int row = wrapi(z - CZ, c.nz) * c.ny + wrapi(y - CY, c.ny);
         Src s[K + 2];
-        ck_column<P, K, ck_needs_edges<Q, CY, CZ>()>(c, row, ci, s);
+        ck_column<P, K, ck_needs_edges<Q, CY, CZ>()>(c, row, ci, nb, s);
         ck_pull<Q, CY, CZ, K>(acc, s);
     }
 }
@@ -154,8 +197,15 @@ __device__ __forceinline__ uint32_t ck_links(const uint32_t (&win)[3][3], int j)
     }
 }
 
+// Occupancy target by chunk length (the register need grows with it: every
+// wave keeps the loads of several neighbour columns in flight): four waves
+// per SIMD for one node, three for two, two for longer chunks.
+constexpr int ck_waves_per_simd(int k) { return k == 1 ? 4 : k == 2 ? 3 : 2; }
+
 template <int Q, int P, int K>
-__global__ __launch_bounds__(kCkThreads) void k_chunks(StepArgs a) {
+__global__ __launch_bounds__(kCkThreads)
+__attribute__((amdgpu_waves_per_eu(ck_waves_per_simd(K))))
+void k_chunks(StepArgs a) {
     using St = Storage<P>;
     constexpr int ES = (int)sizeof(typename St::S);
     const int wave = threadIdx.x >> 6;
@@ -164,8 +214,10 @@ __global__ __launch_bounds__(kCkThreads) void k_chunks(StepArgs a) {
     typedef int wi4 __attribute__((ext_vector_type(4)));
     typedef const __attribute__((address_space(4))) wi4 item_t;
     const wi4 t = ((item_t*)a.tiles)[item];
+    // lanes past the item's chunks repeat the first chunk and store nothing
+    // (all lanes stay active: edge values move between lanes)
     const int lane = __lane_id();
-    if (lane >= t.z) return;
+    const bool valid = lane < t.z;
     const SampleDev* sd = a.samples + t.x;
 
     CkCtx c;
@@ -185,11 +237,23 @@ __global__ __launch_bounds__(kCkThreads) void k_chunks(StepArgs a) {
     c.isr = inv_scale_rho<P>(a);
     c.isu = inv_scale_u<P>(a);
 
-    const int p = t.y + lane;  // packed index of the lane's chunk
+    const int p = t.y + (valid ? lane : 0);  // packed index of the lane's chunk
     const uint32_t e = reinterpret_cast<const uint32_t*>(a.base + uniform64(sd->chunk_list))[p];
     const int row = (int)(e >> kChunkBits), ci = (int)(e & ((1u << kChunkBits) - 1u));
     const int y = row % c.ny, z = row / c.ny;
     const int x0 = ci * K;
+    // list entries grow with the packed index, so lane l - 1 holds chunk
+    // ci - 1 of the same row exactly when its entry is e - 1 (and ci > 0)
+    CkNb nb;
+    {
+        const int ei = (int)e;
+        const int ep = __builtin_amdgcn_update_dpp(0, ei, 0x13C, 0xf, 0xf, false);
+        const int en = __builtin_amdgcn_update_dpp(0, ei, 0x134, 0xf, 0xf, false);
+        nb.left = lane > 0 && valid && ci > 0 && ep == ei - 1;
+        nb.right = lane + 1 < t.z && ci + 1 < c.nch && en == ei + 1;
+        nb.cl = ci == 0 ? c.nch - 1 : ci - 1;
+        nb.cr = ci == c.nch - 1 ? 0 : ci + 1;
+    }
 
     // solid windows of the nine neighbour rows: bit b is node x0 - 1 + b
     uint32_t win[3][3];
@@ -207,20 +271,20 @@ __global__ __launch_bounds__(kCkThreads) void k_chunks(StepArgs a) {
         for (int j = 0; j < K; ++j) acc[comp][j] = 0.0f;
 
     // source plane z - 1 (directions with c_z = +1): own row, row y-1, row y+1
-    ck_source<Q, P, 0, 1, K>(c, y, z, ci, acc);
-    ck_source<Q, P, 1, 1, K>(c, y, z, ci, acc);
-    ck_source<Q, P, -1, 1, K>(c, y, z, ci, acc);
+    ck_source<Q, P, 0, 1, K>(c, y, z, ci, nb, acc);
+    ck_source<Q, P, 1, 1, K>(c, y, z, ci, nb, acc);
+    ck_source<Q, P, -1, 1, K>(c, y, z, ci, nb, acc);
     // source plane z: own row (c_y = c_z = 0), the rest population, rows y-1, y+1
     Src own[K + 2];
-    ck_column<P, K, true>(c, row, ci, own);
+    ck_column<P, K, true>(c, row, ci, nb, own);
     ck_pull<Q, 0, 0, K>(acc, own);
     {
         constexpr float w0 = (float)weight<Q>(0);
 #pragma unroll
         for (int j = 0; j < K; ++j) acc[0][j] = __builtin_fmaf(w0, own[j + 1].a, acc[0][j]);
     }
-    ck_source<Q, P, 1, 0, K>(c, y, z, ci, acc);
-    ck_source<Q, P, -1, 0, K>(c, y, z, ci, acc);
+    ck_source<Q, P, 1, 0, K>(c, y, z, ci, nb, acc);
+    ck_source<Q, P, -1, 0, K>(c, y, z, ci, nb, acc);
     // wall returns of the fluid nodes with a solid link (for the others the
     // z-march adds zeros, which leaves the sums as they are)
     uint32_t fluid = 0;
@@ -237,9 +301,9 @@ __global__ __launch_bounds__(kCkThreads) void k_chunks(StepArgs a) {
         }
     }
     // source plane z + 1 (directions with c_z = -1)
-    ck_source<Q, P, 0, -1, K>(c, y, z, ci, acc);
-    ck_source<Q, P, 1, -1, K>(c, y, z, ci, acc);
-    ck_source<Q, P, -1, -1, K>(c, y, z, ci, acc);
+    ck_source<Q, P, 0, -1, K>(c, y, z, ci, nb, acc);
+    ck_source<Q, P, 1, -1, K>(c, y, z, ci, nb, acc);
+    ck_source<Q, P, -1, -1, K>(c, y, z, ci, nb, acc);
 
     // finalise (as the z-march) and store the chunk, solid slots as zeros
     const float gx = 2.0f * a.ghf[0], gy = 2.0f * a.ghf[1], gz = 2.0f * a.ghf[2];
@@ -255,7 +319,9 @@ __global__ __launch_bounds__(kCkThreads) void k_chunks(StepArgs a) {
         oz[j] = f ? __builtin_fmaf(acc[3][j], r, gz) : 0.0f;
     }
     const float sr = scale_rho<P>(a), su = scale_u<P>(a);
-    const uint32_t vo = (uint32_t)p * (uint32_t)(K * ES), ab = (uint32_t)c.abytes;
+    // a lane past the item's chunks stores out of range (dropped)
+    const uint32_t vo = valid ? (uint32_t)p * (uint32_t)(K * ES) : (uint32_t)kOob;
+    const uint32_t ab = (uint32_t)c.abytes;
     store_chunk<P, K>(c.post, (int)vo, 0, od, sr);
     store_chunk<P, K>(c.post, (int)(vo + ab), 0, ox, su);
     store_chunk<P, K>(c.post, (int)(vo + 2 * ab), 0, oy, su);
