@@ -328,6 +328,7 @@ struct tau1_ctx {
     // z-march launches: one per lane layout present, each over its samples' items
     struct ZGroup {
         int variant;
+        int tile;     // its tile (the autotuner picks one per lane layout)
         bool packed;  // its samples use the packed layout
         StepArgs args[2];
     };
@@ -403,6 +404,7 @@ void* pick_d2q9(int p) {
 // per-node gather over every sample (kernel 0) or the D2Q9 kernel (2).
 Launch step_launch(const tau1_ctx* ctx, int kernel, int tile, int g) {
     Launch l{};
+    if (kernel == 1) tile = ctx->zgroups[g].tile;
     if (kernel == 1 && tile == kChunkTile && ctx->zgroups[g].packed) {
         const auto& grp = ctx->zgroups[g];
         l.fn = pick_chunks(ctx->lattice, ctx->precision, kVariants[grp.variant].k);
@@ -444,6 +446,16 @@ tau1_status launch_one(tau1_ctx* ctx, int kernel, int tile, int parity) {
         void* params[] = {launch_args(ctx, kernel, g, parity)};
         HIP_TRY(hipLaunchKernel(l.fn, l.grid, l.block, params, l.shmem, ctx->stream));
     }
+    return TAU1_OK;
+}
+
+// The launch of lane-layout group g alone (autotune trials).
+tau1_status launch_group(tau1_ctx* ctx, int g, int parity) {
+    const Launch l = step_launch(ctx, 1, ctx->zgroups[g].tile, g);
+    if (!l.fn) return TAU1_E_UNSUPPORTED;
+    if (l.grid.x == 0) return TAU1_OK;
+    void* params[] = {launch_args(ctx, 1, g, parity)};
+    HIP_TRY(hipLaunchKernel(l.fn, l.grid, l.block, params, l.shmem, ctx->stream));
     return TAU1_OK;
 }
 
@@ -720,9 +732,11 @@ tau1_status reduce_ws(tau1_ctx* ctx, int s, int axis, double out[4]) {
     return TAU1_OK;
 }
 
-// Selects the z-march tile (z-segment length), rebuilds and uploads the work
-// list; cached graphs are rebuilt on the next step.
-tau1_status set_tile(tau1_ctx* ctx, int tile) {
+// Selects the tile of every lane layout (`tile`, or per_variant[v] where
+// that is given and not negative), rebuilds and uploads the work lists;
+// cached graphs are rebuilt on the next step.  The context's tile is that of
+// the layout with the most fluid nodes.
+tau1_status set_tile(tau1_ctx* ctx, int tile, const int* per_variant = nullptr) {
     // lane layouts present, the one with the most fluid nodes first (the
     // order of the launches of a step when they run one after another)
     std::vector<int> layouts;
@@ -741,10 +755,11 @@ tau1_status set_tile(tau1_ctx* ctx, int tile) {
         const int64_t item0 = (int64_t)tl.size() / 4;
         tau1_ctx::ZGroup g;
         g.variant = v;
+        g.tile = per_variant && per_variant[v] >= 0 ? per_variant[v] : tile;
         g.packed = false;
         for (const auto& sh : ctx->plan.s)
             if (sh.dev.variant == v && sh.dev.pk) g.packed = true;
-        if (tile == kChunkTile && g.packed) {
+        if (g.tile == kChunkTile && g.packed) {
             // the chunk kernel: one item per 64 stored chunks of a sample
             for (int i = 0; i < ctx->nsamples; ++i) {
                 const auto& sh = ctx->plan.s[i];
@@ -757,7 +772,7 @@ tau1_status set_tile(tau1_ctx* ctx, int tile) {
                 }
             }
         } else {
-            const int zt = tile_zmarch(tile);
+            const int zt = tile_zmarch(g.tile);
             std::vector<int32_t> part =
                 zmarch_worklist(ctx->plan.s.data(), ctx->nsamples, tile_lz(zt), v,
                                 zr_share(kVariants[v].g, tile_mode(zt)));
@@ -781,7 +796,7 @@ tau1_status set_tile(tau1_ctx* ctx, int tile) {
     destroy_graph(ctx);
     ctx->zgroups.swap(groups);
     ctx->args[0].ntiles = ctx->args[1].ntiles = (int32_t)items;
-    ctx->tile = tile;
+    ctx->tile = ctx->zgroups.empty() ? tile : ctx->zgroups[0].tile;
     return TAU1_OK;
 }
 
@@ -1093,24 +1108,38 @@ tau1_status tau1_autotune(tau1_ctx* ctx, int32_t trial_steps) {
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
+    // each lane layout's launch is timed alone at every tile: the layouts of
+    // a batch (rows of different lengths, samples of different depths) may
+    // prefer different z-segments
+    std::vector<float> best_v(kNumVariants, 1e30f);
+    std::vector<int> tile_v(kNumVariants, -1);
     float best = 1e30f;
     int best_tile = ctx->tile;
-    for (int t = 0; t < kNumTiles; ++t) {
+    for (int t = 0; t < kNumTiles && st == TAU1_OK; ++t) {
         if (!zmarch_tile_ok(ctx->precision, ctx->plan.packed, t)) continue;
         st = set_tile(ctx, t);
         if (st != TAU1_OK) break;
-        // the trial reads the current buffer and writes the spare one only
-        st = launch_one(ctx, 1, t, ctx->parity);
-        if (st != TAU1_OK) break;
-        HIP_TRY(hipEventRecord(e0, ctx->stream));
-        for (int i = 0; i < trial_steps && st == TAU1_OK; ++i)
-            st = launch_one(ctx, 1, t, ctx->parity);
-        HIP_TRY(hipEventRecord(e1, ctx->stream));
-        HIP_TRY(hipEventSynchronize(e1));
-        float ms = 0;
-        HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
-        if (ms < best) {
-            best = ms;
+        float total = 0.0f;
+        for (int g = 0; g < (int)ctx->zgroups.size() && st == TAU1_OK; ++g) {
+            // the trial reads the current buffer and writes the spare one only
+            st = launch_group(ctx, g, ctx->parity);
+            if (st != TAU1_OK) break;
+            HIP_TRY(hipEventRecord(e0, ctx->stream));
+            for (int i = 0; i < trial_steps && st == TAU1_OK; ++i)
+                st = launch_group(ctx, g, ctx->parity);
+            HIP_TRY(hipEventRecord(e1, ctx->stream));
+            HIP_TRY(hipEventSynchronize(e1));
+            float ms = 0;
+            HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+            total += ms;
+            const int v = ctx->zgroups[g].variant;
+            if (ms < best_v[v]) {
+                best_v[v] = ms;
+                tile_v[v] = t;
+            }
+        }
+        if (st == TAU1_OK && total < best) {
+            best = total;
             best_tile = t;
         }
     }
@@ -1118,8 +1147,9 @@ tau1_status tau1_autotune(tau1_ctx* ctx, int32_t trial_steps) {
     (void)hipEventDestroy(e1);
     if (st != TAU1_OK) return st;
     ctx->kernel = 1;
-    st = set_tile(ctx, best_tile);
+    st = set_tile(ctx, best_tile, tile_v.data());
     if (st != TAU1_OK) return st;
+    // the cache keeps one tile per size bucket: the best single tile
     if (!ctx->cache.empty())
         zmarch_cache_store(ctx->cache.c_str(), ctx->lattice, ctx->precision, ctx->n_nodes,
                            best_tile, best / trial_steps);
