@@ -21,9 +21,11 @@ Sections (``--sections``, default all):
              of the library (the same crop against the FP64 oracle is a GPU
              test).
   batch      64 uneven porous samples (sides 64..320, porosity U[0.4, 0.95],
-             radius U[4, 16], seeds 5000+i) in one launch per step, 100-step
-             graphs, autotuned tiles, 1000 steps; against the same samples run
-             one by one.
+             radius U[4, 16], seeds 5000+i) in one launch per step and row
+             length (lane layout), the launches as independent graph chains,
+             100-step graphs, a tuned tile per layout, 1000 steps; then with
+             the launches of a step in one chain; against the same samples
+             run one by one.
   validation the paper's 2-D validation runs on the D2Q9 kernel: pressure-
              driven Poiseuille flow on 1000 x 100 (rho 1.01 / 0.99 Zou-He
              columns, halfway walls) run to the steady state (velocity change
@@ -33,11 +35,12 @@ Sections (``--sections``, default all):
              1 % over 10000 steps.
   porosity   D3Q19 FP32 on 256^3 sphere packings (r = 8, target porosity 0.05,
              0.1, 0.2, 0.3, 0.5, 0.6, 0.7, 0.8, 0.9, seeds 2000+i), 1000 steps
-             each: the z-march on the packed and the dense state layouts;
-             permeability,
-             work items visited, and the chunk statistics of the paper's
-             bandwidth model for porous media (fraction of lane chunks stored,
-             mean porosity of the stored chunks, share of mixed chunks).
+             each: the packed state layout at the autotuned tile (a z-march
+             tile, or the chunk tile for mostly solid media) and the dense
+             layout's z-march; permeability, work items visited, and the chunk
+             statistics of the paper's bandwidth model for porous media
+             (fraction of lane chunks stored, mean porosity of the stored
+             chunks, share of mixed chunks), with Eq. (13) fitted to the rates.
 The oracle leg (``cpu_baseline``) times the FP64 CPU oracle on about 15 s of
 steps of the main workload on the host cores.
 

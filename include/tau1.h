@@ -94,8 +94,9 @@ typedef struct {
 typedef struct {
     int32_t lattice;        /* tau1_lattice                                    */
     int32_t precision;      /* tau1_precision                                  */
-    int32_t n_samples;      /* >= 1; > 1 = batched: samples with the same nx
-                               share one kernel launch per step            */
+    int32_t n_samples;      /* >= 1; > 1 = batched: the samples of one lane
+                               layout (row length nx) share one kernel launch
+                               per step, each layout its own launch         */
     int32_t graph_chunk;    /* steps per captured HIP graph; even; 0 = 100      */
     const tau1_sample *samples;
     double g[3];            /* body acceleration, same for every sample         */

@@ -183,17 +183,16 @@ __device__ __forceinline__ void ck_source(const CkCtx& c, int y, int z, int ci, 
     }
 }
 
-// Solid links of node j (bit k - 1: neighbour x + c_k is solid) from the
-// nine mask windows win[CY + 1][CZ + 1], whose bit b is node x0 - 1 + b.
+// Solid neighbours per direction: bit j of m[k] is set when node x0 + j + c_k
+// is solid, from the nine mask windows win[CY + 1][CZ + 1] (bit b: node
+// x0 - 1 + b).  One shift per direction serves all K nodes of the chunk.
 template <int Q, int KD = 1>
-__device__ __forceinline__ uint32_t ck_links(const uint32_t (&win)[3][3], int j) {
-    if constexpr (KD >= Q) {
-        return 0u;
-    } else {
+__device__ __forceinline__ void ck_solid_dirs(const uint32_t (&win)[3][3], uint32_t (&m)[Q]) {
+    if constexpr (KD < Q) {
         using L = Lattice<Q>;
         constexpr int CX = L::c[KD].x, CY = L::c[KD].y, CZ = L::c[KD].z;
-        const uint32_t b = (win[CY + 1][CZ + 1] >> (j + 1 + CX)) & 1u;
-        return (b << (KD - 1)) | ck_links<Q, KD + 1>(win, j);
+        m[KD] = win[CY + 1][CZ + 1] >> (1 + CX);
+        ck_solid_dirs<Q, KD + 1>(win, m);
     }
 }
 
@@ -287,15 +286,19 @@ void k_chunks(StepArgs a) {
     ck_source<Q, P, -1, 0, K>(c, y, z, ci, nb, acc);
     // wall returns of the fluid nodes with a solid link (for the others the
     // z-march adds zeros, which leaves the sums as they are)
-    uint32_t fluid = 0;
+    uint32_t sdir[Q];
+    sdir[0] = 0u;
+    ck_solid_dirs<Q>(win, sdir);
+    uint32_t any = 0;
+#pragma unroll
+    for (int k = 1; k < Q; ++k) any |= sdir[k];
+    const uint32_t fluid = ~(win[1][1] >> 1) & ((1u << K) - 1u);
 #pragma unroll
     for (int j = 0; j < K; ++j) {
-        const bool f = !((win[1][1] >> (j + 1)) & 1u);
-        fluid |= (uint32_t)f << j;
-        const uint32_t links = ck_links<Q>(win, j);
-        if (f && links != 0u) {
+        if ((fluid & any) >> j & 1u) {
             float r[4];
-            wall_sums<Q>(own[j + 1], links, r);
+            wall_sums<Q>(own[j + 1],
+                         [&](int k) { return (uint32_t)__builtin_amdgcn_sbfe((int)sdir[k], j, 1); }, r);
 #pragma unroll
             for (int comp = 0; comp < 4; ++comp) acc[comp][j] += r[comp];
         }

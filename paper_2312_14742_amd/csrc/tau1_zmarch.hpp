@@ -386,35 +386,35 @@ __device__ __forceinline__ void push_row(Planes<C * K>& pl, const Src (&s)[C * K
 }
 
 // Bounce-back sums of one wall node (one per worker lane): every direction k
-// whose neighbour x + c_k is solid (bit k - 1 of `links`) returns the node's
-// own equilibrium in k along -c_k.  Sums are kept per weight class and
-// weighted at the end.
-template <int Q, int KD = 1>
-__device__ __forceinline__ void bounce_sum(const Src& s, uint32_t links, float (&d)[3],
+// whose neighbour x + c_k is solid returns the node's own equilibrium in k
+// along -c_k.  Sums are kept per weight class and weighted at the end.
+// link(k) is all ones when the neighbour x + c_k is solid, else zero (the
+// step kernels keep the solid links in different forms).
+template <int Q, int KD = 1, typename Link>
+__device__ __forceinline__ void bounce_sum(const Src& s, const Link& link, float (&d)[3],
                                            float (&j)[3][3]) {
     if constexpr (KD < Q) {
         using L = Lattice<Q>;
         constexpr int CX = L::c[KD].x, CY = L::c[KD].y, CZ = L::c[KD].z;
         constexpr int cls = (CX != 0) + (CY != 0) + (CZ != 0) - 1;  // face, edge, corner
-        // all-ones when the neighbour x + c_k is solid
-        const uint32_t m = (uint32_t)__builtin_amdgcn_sbfe((int)links, KD - 1, 1);
+        const uint32_t m = link(KD);
         const float u = __builtin_bit_cast(float, __builtin_bit_cast(uint32_t, feq_m<CX, CY, CZ>(s)) & m);
         d[cls] += u;
         if constexpr (CX != 0) j[cls][0] -= CX * u;
         if constexpr (CY != 0) j[cls][1] -= CY * u;
         if constexpr (CZ != 0) j[cls][2] -= CZ * u;
-        bounce_sum<Q, KD + 1>(s, links, d, j);
+        bounce_sum<Q, KD + 1>(s, link, d, j);
     }
 }
 
 // Weighted wall returns of one node: density and momentum (r[0], r[1..3]) of
 // the populations its solid links send back.  The step kernels all add these
 // four values to the node's sums at the same point, so they share this code.
-template <int Q>
-__device__ __forceinline__ void wall_sums(const Src& sw, uint32_t links, float (&r)[4]) {
+template <int Q, typename Link>
+__device__ __forceinline__ void wall_sums(const Src& sw, const Link& link, float (&r)[4]) {
     float sd[3] = {0.f, 0.f, 0.f};
     float sj[3][3] = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};
-    bounce_sum<Q>(sw, links, sd, sj);
+    bounce_sum<Q>(sw, link, sd, sj);
     constexpr float wf = (float)Lattice<Q>::w_face, we = (float)Lattice<Q>::w_edge,
                     wc = (float)Lattice<Q>::w_corner;
     r[0] = wf * sd[0] + we * sd[1] + wc * sd[2];
@@ -768,7 +768,8 @@ __device__ __forceinline__ void bounce_list(const ZrItem<P, G, C, K>& it, Plane<
                 sw = make_src(v[0], v[1], v[2], v[3]);
             }
             float r[4];
-            wall_sums<Q>(sw, links, r);
+            // bit k - 1 of the entry's links: the neighbour x + c_k is solid
+            wall_sums<Q>(sw, [&](int k) { return (uint32_t)__builtin_amdgcn_sbfe((int)links, k - 1, 1); }, r);
 #pragma unroll
             for (int c = 0; c < 4; ++c) res[c * RS + n] = r[c];
         }
