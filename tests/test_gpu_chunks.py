@@ -114,6 +114,35 @@ def test_chunks_batch_mixed_layouts():
     sim.close()
 
 
+def test_chunks_all_solid_and_all_fluid_samples():
+    """Degenerate samples in one chunk-tile batch: an all-solid sample (no
+    stored chunk, no work item), an all-fluid one (every chunk stored, every
+    lane's x-neighbours in the neighbouring lanes), and a sample whose only
+    fluid is one chunk per row at the periodic x wrap (chunks 0 and nch - 1)."""
+    g = (1e-5, -1e-5, 2e-6)
+    rng = np.random.Generator(np.random.PCG64(9600))
+    solid_all = np.ones((4, 5, 256), np.uint8)
+    fluid_all = np.zeros((3, 4, 256), np.uint8)
+    wrap = np.ones((5, 6, 256), np.uint8)
+    wrap[:, :, :3] = 0          # chunk 0 (nodes 0-3) partly fluid
+    wrap[:, :, -2:] = 0         # chunk 63 (nodes 252-255) partly fluid
+    samples = []
+    for solid in (solid_all, fluid_all, wrap):
+        fl = solid == 0
+        drho = np.where(fl, rng.uniform(-1e-3, 1e-3, solid.shape), 0.0)
+        u = np.where(fl, rng.uniform(-0.02, 0.02, (3,) + solid.shape), 0.0)
+        samples.append((solid, drho, u))
+    print("[case] chunks degenerate samples", flush=True)
+    ck = tau1.Sim([tau1.Sample(*s) for s in samples], lattice=19, precision="f32", g=g,
+                  kernel=1, tile=CHUNK_TILE)
+    ck.step(6)
+    for i, s in enumerate(samples):
+        zm, oz = run([s], 19, "f32", g, 6, tile=12)
+        assert_same(ck.moments(i), oz[0], ("degenerate", i))
+        zm.close()
+    ck.close()
+
+
 def test_chunks_graph_replays():
     """100 steps as 10-step graph replays equal 100 single launches."""
     solid, drho, u = inputs.random_state(128, 6, 8, seed=9500, solid_frac=0.9)
