@@ -153,7 +153,10 @@ typedef struct {
     int32_t lattice, precision, n_samples;
     int32_t kernel;          /* step kernel in use: 0 per-node gather,
                                 1 z-march tiles, 2 D2Q9                     */
-    int32_t tile;            /* tile shape index in use (z-march)           */
+    int32_t tile;            /* tile in use (z-march tiles and the chunk
+                                tile); in a batch, that of the lane layout
+                                with the most fluid nodes (tau1_autotune
+                                gives each layout its own)                 */
     int32_t graph_chunk;
     int32_t layout;          /* 1 if any sample is stored packed, else 0    */
     int64_t n_nodes;         /* all samples                                 */
@@ -162,9 +165,10 @@ typedef struct {
     double bytes_per_step;   /* algorithmic HBM bytes of one step (all samples):
                                 2 (d+1) s per fluid node plus one mask bit per
                                 node (complexity table of the paper)        */
-    int64_t work_items;      /* z-march work items per step (row groups x
-                                z-segments holding a fluid node), 0 for the
-                                gather kernel                               */
+    int64_t work_items;      /* work items per step: z-march row groups x
+                                z-segments holding a fluid node, or waves of
+                                64 stored chunks for the chunk tile; 0 for
+                                the gather kernel                           */
 } tau1_info;
 
 /* Bytes of device workspace the descriptor needs: two copies of the state
