@@ -1115,7 +1115,12 @@ tau1_status tau1_autotune(tau1_ctx* ctx, int32_t trial_steps) {
     std::vector<int> tile_v(kNumVariants, -1);
     float best = 1e30f;
     int best_tile = ctx->tile;
-    for (int t = 0; t < kNumTiles && st == TAU1_OK; ++t) {
+    for (int i = 0; i < kNumTiles && st == TAU1_OK; ++i) {
+        // the chunk tile first: its launches load the card less than the
+        // z-march's, and a card that has just run lighter launches runs the
+        // next heavy ones at a transiently higher, then lower clock; ending
+        // with the z-march tiles leaves it as the usual choice runs it
+        const int t = i == 0 ? kChunkTile : i - 1;
         if (!zmarch_tile_ok(ctx->precision, ctx->plan.packed, t)) continue;
         st = set_tile(ctx, t);
         if (st != TAU1_OK) break;
