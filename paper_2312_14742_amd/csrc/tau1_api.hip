@@ -34,6 +34,7 @@ struct SampleHost {
     int64_t n_fluid;
     std::vector<uint32_t> ctab;  // packed layout: chunk table (4 words per entry)
     int64_t nch = 0;             // packed layout: stored chunks
+    bool ck = false;             // holds the chunk list and neighbour records
     std::vector<uint8_t> rowfluid;  // z-march samples: 1 if row y + ny z holds a fluid node
 };
 
@@ -157,6 +158,38 @@ __global__ void k_chunk_list(const ct_u4* __restrict__ tab, uint32_t* __restrict
     }
 }
 
+// Neighbour-row records of a packed sample's stored chunks (the chunk
+// tile's addressing), from its chunk table and list: one thread per stored
+// chunk, nine records each (rows y + dy, z + dz, record (dy + 1) * 3 + dz + 1),
+// stored as nine arrays of nch records.
+__global__ void k_chunk_nbr(const ct_u4* __restrict__ tab, const uint32_t* __restrict__ list,
+                            ck_rec_t* __restrict__ rec, int ny, int nz, int groups, int nrow,
+                            int64_t nch) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= nch) return;
+    const uint32_t e = list[p];
+    const int row = (int)(e >> kChunkBits), ci = (int)(e & ((1u << kChunkBits) - 1u));
+    const int y = row % ny, z = row / ny;
+    for (int dy = -1; dy <= 1; ++dy)
+        for (int dz = -1; dz <= 1; ++dz) {
+            const int yy = (y + dy + ny) % ny, zz = (z + dz + nz) % nz;
+            const ct_u4* tr = tab + ((int64_t)zz * ny + yy) * groups;
+            auto bits_of = [&](int g) { return ((uint64_t)tr[g].y << 32) | tr[g].x; };
+            auto stored = [&](int cj) { return (uint32_t)((bits_of(cj >> 6) >> (cj & 63)) & 1u); };
+            auto rank = [&](int cj) {
+                const uint64_t below = bits_of(cj >> 6) & ((uint64_t(1) << (cj & 63)) - 1u);
+                return tr[cj >> 6].z + (uint32_t)__popcll(below);
+            };
+            ck_rec_t r;
+            r.x = rank(ci) | (ci > 0 ? stored(ci - 1) << 29 : 0u) | (stored(ci) << 30) |
+                  (ci + 1 < nrow ? stored(ci + 1) << 31 : 0u);
+            r.y = 0u;
+            if (ci == 0 && stored(nrow - 1)) r.y = rank(nrow - 1) | (1u << 31);
+            if (ci == nrow - 1 && stored(0)) r.y = rank(0) | (1u << 31);
+            rec[(int64_t)((dy + 1) * 3 + dz + 1) * nch + p] = r;
+        }
+}
+
 // Workspace plan; `tables` also builds the packed layout's chunk tables
 // (the size query only counts chunks).
 Plan make_plan(const tau1_desc* d, bool tables) {
@@ -218,18 +251,28 @@ Plan make_plan(const tau1_desc* d, bool tables) {
             chunk_table(d->samples[i], k, groups, p.s[i].ctab.data());
         }
         sd.pk = k;
+        sd.nchunks = p.s[i].nch;
         sd.stride = pstride[i];
         p.packed = true;
     }
     for (auto& sh : p.s)
         if (!sh.dev.pk) sh.nch = 0;  // counted, but its lane layout stays dense
+    // The chunk tile's list and neighbour records (76 B per stored chunk):
+    // where the chunk tile is asked for, or where at most half of the
+    // sample's chunks are stored (the media the chunk tile is for).
+    for (auto& sh : p.s) {
+        if (!sh.dev.pk) continue;
+        const int64_t all = (int64_t)sh.dev.ny * sh.dev.nz * (sh.dev.nx / sh.dev.pk);
+        sh.ck = (d->tile == kChunkTile || 2 * sh.nch <= all) && sh.nch <= (int64_t)kRecIndex;
+    }
     p.pack_refused = d->layout == 1 && !p.packed;
     // work-list capacity: the longest z-march list (16-plane segments) or the
     // chunk tile's list (one item per 64 stored chunks), whichever is longer
     tiles = zmarch_max_items(p.s.data(), d->n_samples);
     {
         int64_t ck = 0;
-        for (const auto& sh : p.s) ck += (sh.nch + 63) / 64;
+        for (const auto& sh : p.s)
+            if (sh.ck) ck += (sh.nch + 63) / 64;
         tiles = std::max(tiles, ck);
     }
     p.total_blocks = blocks;
@@ -252,8 +295,13 @@ Plan make_plan(const tau1_desc* d, bool tables) {
         if (sd.pk) {
             sd.chunk_tab = (int64_t)off;
             off = align_up(off + 16 * (size_t)sd.ny * sd.nz * kVariants[sd.variant].c, kAlign);
-            sd.chunk_list = (int64_t)off;
-            off = align_up(off + 4 * (size_t)std::max<int64_t>(p.s[i].nch, 1), kAlign);
+            if (p.s[i].ck) {
+                const size_t nch = (size_t)std::max<int64_t>(p.s[i].nch, 1);
+                sd.chunk_list = (int64_t)off;
+                off = align_up(off + 4 * nch, kAlign);
+                sd.chunk_nbr = (int64_t)off;
+                off = align_up(off + 9 * 8 * nch, kAlign);
+            }
         }
         if (d->lattice == 9) {
             sd.types = (int64_t)off;
@@ -330,6 +378,7 @@ struct tau1_ctx {
         int variant;
         int tile;     // its tile (the autotuner picks one per lane layout)
         bool packed;  // its samples use the packed layout
+        bool chunks;  // ... and hold the chunk tile's list and records
         StepArgs args[2];
     };
     std::vector<ZGroup> zgroups;
@@ -405,7 +454,7 @@ void* pick_d2q9(int p) {
 Launch step_launch(const tau1_ctx* ctx, int kernel, int tile, int g) {
     Launch l{};
     if (kernel == 1) tile = ctx->zgroups[g].tile;
-    if (kernel == 1 && tile == kChunkTile && ctx->zgroups[g].packed) {
+    if (kernel == 1 && tile == kChunkTile && ctx->zgroups[g].chunks) {
         const auto& grp = ctx->zgroups[g];
         l.fn = pick_chunks(ctx->lattice, ctx->precision, kVariants[grp.variant].k);
         l.block = dim3(kCkThreads);
@@ -447,6 +496,13 @@ tau1_status launch_one(tau1_ctx* ctx, int kernel, int tile, int parity) {
         HIP_TRY(hipLaunchKernel(l.fn, l.grid, l.block, params, l.shmem, ctx->stream));
     }
     return TAU1_OK;
+}
+
+// Whether some sample holds the chunk tile's list and records.
+bool any_chunks(const tau1_ctx* ctx) {
+    for (const auto& sh : ctx->plan.s)
+        if (sh.dev.chunk_list) return true;
+    return false;
 }
 
 // The launch of lane-layout group g alone (autotune trials).
@@ -615,13 +671,26 @@ tau1_status upload_sample_t(tau1_ctx* ctx, int s, const tau1_sample& in) {
         const auto& tab = ctx->plan.s[s].ctab;
         HIP_TRY(hipMemcpyAsync(ctx->base + sd.chunk_tab, tab.data(), sizeof(uint32_t) * tab.size(),
                                hipMemcpyHostToDevice, ctx->stream));
-        // chunk list (the chunk tile's work), from the table on the device
+        HIP_TRY(hipStreamSynchronize(ctx->stream));
+    }
+    if (sd.chunk_list) {
+        // chunk list (the chunk tile's work) and neighbour records, from the
+        // table on the device
         const int groups = kVariants[sd.variant].c;
         const int64_t entries = (int64_t)sd.ny * sd.nz * groups;
+        const ct_u4* tab = reinterpret_cast<const ct_u4*>(ctx->base + sd.chunk_tab);
+        uint32_t* list = reinterpret_cast<uint32_t*>(ctx->base + sd.chunk_list);
         hipLaunchKernelGGL(k_chunk_list, dim3((unsigned)((entries + 255) / 256)), dim3(256), 0,
-                           ctx->stream, reinterpret_cast<const ct_u4*>(ctx->base + sd.chunk_tab),
-                           reinterpret_cast<uint32_t*>(ctx->base + sd.chunk_list), groups, entries);
+                           ctx->stream, tab, list, groups, entries);
         HIP_TRY(hipGetLastError());
+        const int64_t nch = ctx->plan.s[s].nch;
+        if (nch > 0) {
+            hipLaunchKernelGGL(k_chunk_nbr, dim3((unsigned)((nch + 255) / 256)), dim3(256), 0,
+                               ctx->stream, tab, list,
+                               reinterpret_cast<ck_rec_t*>(ctx->base + sd.chunk_nbr), sd.ny, sd.nz,
+                               groups, sd.nx / sd.pk, nch);
+            HIP_TRY(hipGetLastError());
+        }
         HIP_TRY(hipStreamSynchronize(ctx->stream));
     }
     // state (the packed layout's upload kernel skips nodes of all-solid chunks)
@@ -757,9 +826,14 @@ tau1_status set_tile(tau1_ctx* ctx, int tile, const int* per_variant = nullptr) 
         g.variant = v;
         g.tile = per_variant && per_variant[v] >= 0 ? per_variant[v] : tile;
         g.packed = false;
+        g.chunks = true;
         for (const auto& sh : ctx->plan.s)
-            if (sh.dev.variant == v && sh.dev.pk) g.packed = true;
-        if (g.tile == kChunkTile && g.packed) {
+            if (sh.dev.variant == v) {
+                if (sh.dev.pk) g.packed = true;
+                if (!sh.dev.chunk_list) g.chunks = false;
+            }
+        g.chunks = g.chunks && g.packed;
+        if (g.tile == kChunkTile && g.chunks) {
             // the chunk kernel: one item per 64 stored chunks of a sample
             for (int i = 0; i < ctx->nsamples; ++i) {
                 const auto& sh = ctx->plan.s[i];
@@ -1122,6 +1196,7 @@ tau1_status tau1_autotune(tau1_ctx* ctx, int32_t trial_steps) {
         // with the z-march tiles leaves it as the usual choice runs it
         const int t = i == 0 ? kChunkTile : i - 1;
         if (!zmarch_tile_ok(ctx->precision, ctx->plan.packed, t)) continue;
+        if (t == kChunkTile && !any_chunks(ctx)) continue;
         st = set_tile(ctx, t);
         if (st != TAU1_OK) break;
         float total = 0.0f;
@@ -1138,6 +1213,9 @@ tau1_status tau1_autotune(tau1_ctx* ctx, int32_t trial_steps) {
             HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
             total += ms;
             const int v = ctx->zgroups[g].variant;
+            // a layout without the chunk records runs a z-march tile in place
+            // of the chunk tile: not a choice of its own
+            if (t == kChunkTile && !ctx->zgroups[g].chunks) continue;
             if (ms < best_v[v]) {
                 best_v[v] = ms;
                 tile_v[v] = t;

@@ -11,10 +11,12 @@
 // neighbours send it (the pull form of Eqs. (9)-(10)): it reads the nine
 // (y, z) neighbour columns of its chunk -- the chunk at the same x-position
 // in each neighbour row, plus the node on either side in x where a direction
-// needs it -- through the chunk table, so an all-solid chunk reads as zeros,
-// which a solid node sends anyway.  Halfway bounce-back (Eq. 11) returns the
-// node's own equilibria along its solid links, which come from the extended
-// solid mask of the same nine rows.
+// needs it -- at the packed positions that the chunk's nine neighbour-row
+// records give (built once from the chunk table, so a step reads the state
+// one dependent load after the records), and an all-solid chunk reads as
+// zeros, which a solid node sends anyway.  Halfway bounce-back (Eq. 11)
+// returns the node's own equilibria along its solid links, which come from
+// the extended solid mask of the same nine rows.
 //
 // Every destination sum is formed in the order in which the z-march forms
 // it: source plane z-1, then z, then z+1; within a plane the own row, then
@@ -52,28 +54,12 @@ constexpr bool ck_needs_edges() {
 }
 
 struct CkCtx {
-    rsrc_t pre, post;                 // the read and the written buffer (four arrays each)
-    int abytes;                       // bytes per array
-    const ct_u4* tab;                 // chunk table of the sample
-    const uint32_t* xm;               // extended solid mask
-    int nx, ny, nz, xw, groups, nch;  // nch: chunks per row
+    rsrc_t pre, post;         // the read and the written buffer (four arrays each)
+    int abytes;               // bytes per array
+    const uint32_t* xm;       // extended solid mask
+    int nx, ny, nz, xw, nch;  // nch: chunks per row
     float isr, isu;
 };
-
-// Byte offset of the chunk with bit l of table entry e (K-node chunks of ES
-// bytes per value), or the out-of-range offset when the chunk is not stored.
-template <int K, int ES>
-__device__ __forceinline__ int ck_slot(const ct_u4& e, int l) {
-    const uint64_t bits = ((uint64_t)e.y << 32) | e.x;
-    const uint64_t below = bits & ((uint64_t(1) << l) - 1u);
-    return ((bits >> l) & 1u) ? (int)((e.z + (uint32_t)__popcll(below)) * (uint32_t)(K * ES)) : kOob;
-}
-
-// Byte offset of chunk cj of row `row` in a state array (or out of range).
-template <int K, int ES>
-__device__ __forceinline__ int ck_offset(const CkCtx& c, int row, int cj) {
-    return ck_slot<K, ES>(c.tab[(int64_t)row * c.groups + (cj >> 6)], cj & 63);
-}
 
 // Lane moves across the whole wave: from lane l - 1 (ror) and from lane l + 1 (rol).
 __device__ __forceinline__ float ck_from_prev(float v) {
@@ -96,19 +82,17 @@ struct CkNb {
 // Source terms of the column's nodes x0 - 1 .. x0 + K (slots 0 .. K + 1); the
 // two edge slots only where a direction of the column needs them.  Every
 // lane of the wave takes part (the edge values move between lanes).  All
-// loads of a column depend only on its table entries, so they are in flight
-// together: the edge reads of lanes whose neighbour lane holds the edge use
-// an out-of-range offset (no memory access) instead of a branch.
+// reads of a column are addressed from its record alone, so they are in
+// flight together; the edge reads of lanes whose neighbour lane holds the
+// edge use an out-of-range offset (no memory access) instead of a branch.
 template <int P, int K, bool EDGES>
-__device__ __forceinline__ void ck_column(const CkCtx& c, int row, int ci, const CkNb& nb,
-                                          Src (&s)[K + 2]) {
+__device__ __forceinline__ void ck_column(const CkCtx& c, const ck_rec_t& rec, int ci,
+                                          const CkNb& nb, Src (&s)[K + 2]) {
     constexpr int ES = (int)sizeof(typename Storage<P>::S);
-    // the row's table entry of the chunk's group, and of the other group
-    // (the same entry when a row has one group); a row has at most two
-    const int64_t rb = (int64_t)row * c.groups;
-    const int g = ci >> 6;
-    const ct_u4 te = c.tab[rb + g];
-    const int vo = ck_slot<K, ES>(te, ci & 63);
+    constexpr uint32_t CB = (uint32_t)(K * ES);
+    const uint32_t rank = rec.x & kRecIndex;
+    const uint32_t sc = (rec.x >> 30) & 1u;
+    const int vo = sc ? (int)(rank * CB) : kOob;
     float v[4][K];
     load_chunk<P, K>(c.pre, vo, 0, v[0], c.isr);
     load_chunk<P, K>(c.pre, vo, c.abytes, v[1], c.isu);
@@ -116,10 +100,16 @@ __device__ __forceinline__ void ck_column(const CkCtx& c, int row, int ci, const
     load_chunk<P, K>(c.pre, vo, 3 * c.abytes, v[3], c.isu);
     float e[2][4];
     if constexpr (EDGES) {
-        const ct_u4 to = c.tab[rb + (g ^ (c.groups - 1))];
-        int ol = ck_slot<K, ES>((nb.cl >> 6) == g ? te : to, nb.cl & 63);
+        // chunk ci - 1 is the stored chunk before position ci, chunk ci + 1 the
+        // one after chunk ci; across the periodic x boundary the record names it
+        const uint32_t wrap = rec.y & kRecIndex;
+        const bool wok = (rec.y >> 31) != 0u;
+        int ol, orr;
+        if (ci > 0) ol = ((rec.x >> 29) & 1u) ? (int)((rank - 1u) * CB) : kOob;
+        else ol = wok ? (int)(wrap * CB) : kOob;
+        if (ci + 1 < c.nch) orr = (rec.x >> 31) ? (int)((rank + sc) * CB) : kOob;
+        else orr = wok ? (int)(wrap * CB) : kOob;
         ol = (nb.left || ol == kOob) ? kOob : ol + (K - 1) * ES;
-        int orr = ck_slot<K, ES>((nb.cr >> 6) == g ? te : to, nb.cr & 63);
         orr = nb.right ? kOob : orr;
         e[0][0] = load_one<P>(c.pre, ol, 0, c.isr);
         e[1][0] = load_one<P>(c.pre, orr, 0, c.isr);
@@ -173,12 +163,11 @@ __device__ __forceinline__ void ck_pull(float (&acc)[4][K], const Src (&s)[K + 2
 // Source column (source row offset -CY, plane offset -CZ from the node): its
 // directions c_y = CY, c_z = CZ.
 template <int Q, int P, int CY, int CZ, int K>
-__device__ __forceinline__ void ck_source(const CkCtx& c, int y, int z, int ci, const CkNb& nb,
-                                          float (&acc)[4][K]) {
+__device__ __forceinline__ void ck_source(const CkCtx& c, const ck_rec_t (&rec)[9], int ci,
+                                          const CkNb& nb, float (&acc)[4][K]) {
     if constexpr (ck_has_dir<Q, CY, CZ>()) {
-        const int row = wrapi(z - CZ, c.nz) * c.ny + wrapi(y - CY, c.ny);
         Src s[K + 2];
-        ck_column<P, K, ck_needs_edges<Q, CY, CZ>()>(c, row, ci, nb, s);
+        ck_column<P, K, ck_needs_edges<Q, CY, CZ>()>(c, rec[(1 - CY) * 3 + 1 - CZ], ci, nb, s);
         ck_pull<Q, CY, CZ, K>(acc, s);
     }
 }
@@ -225,19 +214,25 @@ void k_chunks(StepArgs a) {
     c.nz = __builtin_amdgcn_readfirstlane(sd->nz);
     c.xw = __builtin_amdgcn_readfirstlane(sd->xwords);
     c.nch = c.nx / K;
-    c.groups = (c.nch + 63) / 64;
     const int64_t stride = uniform64(sd->stride);
     c.abytes = (int)(uint32_t)(stride * ES);
     const int64_t st0 = uniform64(sd->state[0]), st1 = uniform64(sd->state[1]);
     c.pre = make_rsrc(a.base + (a.parity ? st1 : st0), 4u * (uint32_t)c.abytes);
     c.post = make_rsrc(a.base + (a.parity ? st0 : st1), 4u * (uint32_t)c.abytes);
-    c.tab = reinterpret_cast<const ct_u4*>(a.base + uniform64(sd->chunk_tab));
     c.xm = reinterpret_cast<const uint32_t*>(a.base + uniform64(sd->xmask));
     c.isr = inv_scale_rho<P>(a);
     c.isu = inv_scale_u<P>(a);
 
     const int p = t.y + (valid ? lane : 0);  // packed index of the lane's chunk
     const uint32_t e = reinterpret_cast<const uint32_t*>(a.base + uniform64(sd->chunk_list))[p];
+    // neighbour-row records: record (dy + 1) * 3 + dz + 1 for row (y + dy, z + dz)
+    ck_rec_t rec[9];
+    {
+        const ck_rec_t* rb = reinterpret_cast<const ck_rec_t*>(a.base + uniform64(sd->chunk_nbr));
+        const int64_t nchunks = uniform64(sd->nchunks);
+#pragma unroll
+        for (int i = 0; i < 9; ++i) rec[i] = rb[(int64_t)i * nchunks + p];
+    }
     const int row = (int)(e >> kChunkBits), ci = (int)(e & ((1u << kChunkBits) - 1u));
     const int y = row % c.ny, z = row / c.ny;
     const int x0 = ci * K;
@@ -270,20 +265,20 @@ void k_chunks(StepArgs a) {
         for (int j = 0; j < K; ++j) acc[comp][j] = 0.0f;
 
     // source plane z - 1 (directions with c_z = +1): own row, row y-1, row y+1
-    ck_source<Q, P, 0, 1, K>(c, y, z, ci, nb, acc);
-    ck_source<Q, P, 1, 1, K>(c, y, z, ci, nb, acc);
-    ck_source<Q, P, -1, 1, K>(c, y, z, ci, nb, acc);
+    ck_source<Q, P, 0, 1, K>(c, rec, ci, nb, acc);
+    ck_source<Q, P, 1, 1, K>(c, rec, ci, nb, acc);
+    ck_source<Q, P, -1, 1, K>(c, rec, ci, nb, acc);
     // source plane z: own row (c_y = c_z = 0), the rest population, rows y-1, y+1
     Src own[K + 2];
-    ck_column<P, K, true>(c, row, ci, nb, own);
+    ck_column<P, K, true>(c, rec[4], ci, nb, own);
     ck_pull<Q, 0, 0, K>(acc, own);
     {
         constexpr float w0 = (float)weight<Q>(0);
 #pragma unroll
         for (int j = 0; j < K; ++j) acc[0][j] = __builtin_fmaf(w0, own[j + 1].a, acc[0][j]);
     }
-    ck_source<Q, P, 1, 0, K>(c, y, z, ci, nb, acc);
-    ck_source<Q, P, -1, 0, K>(c, y, z, ci, nb, acc);
+    ck_source<Q, P, 1, 0, K>(c, rec, ci, nb, acc);
+    ck_source<Q, P, -1, 0, K>(c, rec, ci, nb, acc);
     // wall returns of the fluid nodes with a solid link (for the others the
     // z-march adds zeros, which leaves the sums as they are)
     uint32_t sdir[Q];
@@ -304,9 +299,9 @@ void k_chunks(StepArgs a) {
         }
     }
     // source plane z + 1 (directions with c_z = -1)
-    ck_source<Q, P, 0, -1, K>(c, y, z, ci, nb, acc);
-    ck_source<Q, P, 1, -1, K>(c, y, z, ci, nb, acc);
-    ck_source<Q, P, -1, -1, K>(c, y, z, ci, nb, acc);
+    ck_source<Q, P, 0, -1, K>(c, rec, ci, nb, acc);
+    ck_source<Q, P, 1, -1, K>(c, rec, ci, nb, acc);
+    ck_source<Q, P, -1, -1, K>(c, rec, ci, nb, acc);
 
     // finalise (as the z-march) and store the chunk, solid slots as zeros
     const float gx = 2.0f * a.ghf[0], gy = 2.0f * a.ghf[1], gz = 2.0f * a.ghf[2];

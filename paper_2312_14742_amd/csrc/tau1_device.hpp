@@ -160,9 +160,14 @@ struct SampleDev {
     int64_t wall_off;     // byte offset of the wall-list row offsets (uint32, rows + 1)
     int64_t wall_list;    // byte offset of the wall-list entries (one per wall node)
     int64_t chunk_tab;    // byte offset of the chunk table (packed layout)
-    int64_t chunk_list;   // byte offset of the chunk list (packed layout): per stored
-                          // chunk, in storage order, row y + ny z (bits 7..31) and
-                          // chunk index in the row (bits 0..6)
+    int64_t chunk_list;   // byte offset of the chunk list (packed layout, where the
+                          // chunk tile may run; else 0): per stored chunk, in
+                          // storage order, row y + ny z (bits 7..31) and chunk
+                          // index in the row (bits 0..6)
+    int64_t chunk_nbr;    // byte offset of the chunks' neighbour-row records (with
+                          // the chunk list; else 0): 9 arrays, one per (y, z)
+                          // neighbour row, of one uint2 per stored chunk
+    int64_t nchunks;      // packed layout: stored chunks
     int64_t types;        // D2Q9: byte offset of the node types (uint8: 0 fluid,
                           // 1 wall, 2 moving wall); 0 otherwise
     int32_t nx, ny, nz;

@@ -440,6 +440,15 @@ __device__ __forceinline__ int64_t uniform64(int64_t v) {
 // the previous plane's stores included -- since loads and stores retire
 // through one in-order counter.
 typedef unsigned int ct_u4 __attribute__((ext_vector_type(4)));
+// Chunk tile: neighbour-row record of a stored chunk (position ci of row r)
+// for one of the nine rows r' = (y + dy, z + dz).  x: packed index of the
+// first stored chunk at or after position ci of r' (bits 0..28), stored flags
+// of positions ci - 1 (bit 29; 0 at ci = 0), ci (bit 30) and ci + 1 (bit 31;
+// 0 at the row's last position).  y: at ci = 0 and at the last position, the
+// packed index of the chunk across the periodic x boundary in r' (bits
+// 0..28) and its stored flag (bit 31); else 0.
+typedef unsigned int ck_rec_t __attribute__((ext_vector_type(2)));
+constexpr unsigned kRecIndex = (1u << 29) - 1u;
 typedef const __attribute__((address_space(4))) ct_u4 ctab_t;
 typedef const __attribute__((address_space(4))) uint32_t wofs_t;
 

@@ -32,19 +32,23 @@ def zmarch_items(solids):
     return sum((s.shape[1] + 3) // 4 * 4 * ((s.shape[0] + 15) // 16) for s in solids)
 
 
-def packed_extra(solids, packed):
+def packed_extra(solids, packed, tile=-1):
     """Workspace the packed layout adds besides its smaller state buffers: per
-    packed sample the chunk table (16 B per row and group) and the chunk list
-    (4 B per stored chunk), and a work list long enough for the chunk tile
-    (one 16-B item per 64 stored chunks of each packed sample)."""
+    packed sample the chunk table (16 B per row and group); where the chunk
+    tile is asked for or at most half of the sample's chunks are stored, the
+    chunk list (4 B per stored chunk) and nine neighbour-row records (8 B
+    each per stored chunk); and a work list long enough for the chunk tile
+    (one 16-B item per 64 stored chunks of each such sample)."""
     extra = 0
     waves = 0
     for s in packed:
         nz, ny, nx = s.shape
         k, groups = G1[nx]
         nch = fluid_chunks(s, k)
-        extra += align(16 * ny * nz * groups) + align(4 * max(nch, 1))
-        waves += (nch + 63) // 64
+        extra += align(16 * ny * nz * groups)
+        if tile == 16 or 2 * nch <= ny * nz * (nx // k):
+            extra += align(4 * max(nch, 1)) + align(72 * max(nch, 1))
+            waves += (nch + 63) // 64
     items = zmarch_items(solids)
     return extra + align(16 * max(items, waves, 1)) - align(16 * max(items, 1))
 
@@ -76,8 +80,11 @@ def test_packed_is_default_for_zmarch_precisions(lib):
     # FP64 runs the per-node gather on the dense layout
     assert tau1.workspace_size([(solid,)], precision="f64") == \
         tau1.workspace_size([(solid,)], precision="f64", layout=0)
-    # the chunk tile belongs to the packed layout
-    assert tau1.workspace_size([(solid,)], tile=16) == tau1.workspace_size([(solid,)], layout=1)
+    # the chunk tile belongs to the packed layout; asked for, it also brings
+    # the chunk list and records of a sample that keeps most of its chunks
+    packed = tau1.workspace_size([(solid,)], layout=1)
+    assert tau1.workspace_size([(solid,)], tile=16) == \
+        packed + packed_extra([solid], [solid], tile=16) - packed_extra([solid], [solid])
     # a dense-layout tile keeps the automatic layout dense
     assert tau1.workspace_size([(solid,)], tile=6) == tau1.workspace_size([(solid,)], layout=0)
     assert tau1.workspace_size([(solid,)], tile=14) == tau1.workspace_size([(solid,)], layout=1)
