@@ -609,6 +609,9 @@ def main(argv=None):
             "roofline": {"bound": "hbm", "achieved": main_res["alg_gbs"],
                          "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": main_res["frac"],
                          "traffic": traffic,
+                         # measured HBM bytes of a launch over its measured time
+                         "traffic_gbs": (traffic / (main_res["launch_ms"] * 1e-3) / 1e9
+                                         if traffic else None),
                          "alg_bytes_per_launch": main_res["bytes_per_step"],
                          "launch_ms": main_res["launch_ms"],
                          "kernel": "tau1::k_zmarch (one launch per step)",
