@@ -143,6 +143,30 @@ def test_chunks_all_solid_and_all_fluid_samples():
     ck.close()
 
 
+def test_autotune_mixed_chunk_records():
+    """A batch where only some lane layouts hold the chunk tile's records (a
+    mostly solid sample gets them, samples that keep most of their chunks do
+    not): the autotuner offers the chunk tile only to the former, and the tuned
+    batch equals the batch at one fixed z-march tile, bit for bit."""
+    g = (1e-5, -2e-6, 1e-6)
+    specs = [((256, 6, 8), 0.95), ((128, 5, 6), 0.3), ((256, 4, 5), 0.3), ((96, 5, 4), 0.97)]
+    samples = [inputs.random_state(nx, ny, nz, seed=9700 + i, solid_frac=sf)
+               for i, ((nx, ny, nz), sf) in enumerate(specs)]
+    print("[case] autotune with and without chunk records", flush=True)
+    fixed = tau1.Sim([tau1.Sample(*s) for s in samples], lattice=19, precision="f32", g=g,
+                     kernel=1, tile=12)
+    fixed.step(6)
+    tuned = tau1.Sim([tau1.Sample(*s) for s in samples], lattice=19, precision="f32", g=g,
+                     kernel=1)
+    tuned.step(2)
+    tuned.autotune(2)
+    tuned.step(4)
+    for i in range(len(samples)):
+        assert_same(tuned.moments(i), fixed.moments(i), ("mixed records", i))
+    fixed.close()
+    tuned.close()
+
+
 def test_chunks_graph_replays():
     """100 steps as 10-step graph replays equal 100 single launches."""
     solid, drho, u = inputs.random_state(128, 6, 8, seed=9500, solid_frac=0.9)
