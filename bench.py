@@ -252,7 +252,7 @@ class GpuRunner:
             "launch_ms": ev / steps * 1e3,
             "alg_gbs": inf["bytes_per_step"] / (ev / steps) / 1e9,
             "tile": inf["tile"], "kernel": inf["kernel"], "layout": inf["layout"],
-            "work_items": inf["work_items"],
+            "work_items": inf["work_items"], "launches_per_step": inf["launches_per_step"],
             "n_fluid": inf["n_fluid"], "n_nodes": inf["n_nodes"],
             "bytes_per_step": inf["bytes_per_step"],
         }
@@ -347,9 +347,18 @@ def batch_section(gr, batch, args, out):
     sim2, res2 = gr.case(samples, 19, "f32", steps, args.graph_chunk, args.graph_chunk,
                          args.tile, label="batched 64 samples, one chain", batch_graph=1)
     sim2.close()
+    # every sample in one launch per step (all rows here are 64-320 nodes long)
+    sim3, res3 = gr.case(samples, 19, "f32", steps, args.graph_chunk, args.graph_chunk,
+                         args.tile, label="batched 64 samples, one launch", batch_graph=3)
+    one_launch_state = {i: sim3.moments(i) for i in probe}
+    sim3.close()
+    keys = ("gflups", "alg_gbs", "frac", "tile", "ms_per_step", "launch_ms", "launches_per_step")
     res["graph"] = "one chain of launches per lane layout, the chains side by side"
-    res["one_chain"] = {k: res2[k] for k in ("gflups", "alg_gbs", "frac", "tile",
-                                             "ms_per_step")}
+    res["one_chain"] = {k: res2[k] for k in keys}
+    res["one_launch"] = {k: res3[k] for k in keys}
+    res["one_launch"]["bitwise_equal_to_chains"] = all(
+        a[0].tobytes() == b[0].tobytes() and a[1].tobytes() == b[1].tobytes()
+        for a, b in ((one_launch_state[i], batched_state[i]) for i in probe))
     if args.no_batch_solo:
         out["batched"] = res
         return

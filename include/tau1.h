@@ -139,12 +139,18 @@ typedef struct {
                                rho_in, at x = nx - 1 rho_out (nx >= 3)      */
     double rho_in, rho_out; /* > 0, used when x_boundary = 1              */
     double wall_u[3];       /* velocity of the moving walls (z ignored)    */
-    /* Graph shape of a batch whose samples need several z-march launches per
-     * step (one per lane layout): 1 = one chain: the launches of a step run
-     * one after another, largest first, each with the whole GPU; 2 = one
-     * chain per lane layout, the chains running side by side; 0 = automatic
-     * (2, measured the faster on the 64-sample batch).  Single-launch
-     * contexts ignore it.                                                   */
+    /* Launch and graph shape of a batch whose samples have several lane
+     * layouts (rows of different lengths; one z-march launch per layout):
+     * 1 = one chain: the launches of a step run one after another, largest
+     * first, each with the whole GPU; 2 = one chain per lane layout, the
+     * chains running side by side; 3 = one launch per step for every sample
+     * whose row is 64-320 nodes long (one lane chunk per row) and whose tile
+     * runs the rows-shared-through-LDS schedule of the leading such layout
+     * (the others, such as rows of 384 or 512 nodes, launch alone, in
+     * chains as with 2); the results are the same bits in every shape;
+     * 0 = automatic (2, measured the faster on the 64-sample batch).
+     * Single-launch contexts ignore it; values outside 0-3 are
+     * TAU1_E_INVALID.                                                        */
     int32_t batch_graph;
 } tau1_desc;
 
@@ -169,6 +175,9 @@ typedef struct {
                                 z-segments holding a fluid node, or waves of
                                 64 stored chunks for the chunk tile; 0 for
                                 the gather kernel                           */
+    int32_t launches_per_step; /* kernel launches one step takes (one per
+                                z-march lane layout, or one for all the
+                                one-chunk rows with batch_graph 3)          */
 } tau1_info;
 
 /* Bytes of device workspace the descriptor needs: two copies of the state

@@ -2,8 +2,9 @@
 
 Run ``python -m paper_2312_14742_amd.build`` or call :func:`build`.  hipcc
 cross-compiles for gfx950 without a GPU present.  The z-march kernels of each
-(lattice, precision) pair are a translation unit of their own, compiled in
-parallel, then linked with the host API into one shared library.
+(lattice, precision) pair are two translation units of their own (the
+per-layout kernels, and the one-launch kernels of a batch's one-row layouts),
+compiled in parallel, then linked with the host API into one shared library.
 """
 from __future__ import annotations
 
@@ -49,6 +50,9 @@ def build(verbose: bool = False, extra: list[str] | None = None, jobs: int | Non
     for q, p in PAIRS:
         units.append((os.path.join(CSRC, "tau1_zmarch_inst.hip"),
                       os.path.join(OBJDIR, f"tau1_zm_{q}_{p}.o"),
+                      [f"-DTAU1_Q={q}", f"-DTAU1_P={p}"]))
+        units.append((os.path.join(CSRC, "tau1_zmarch_rows.hip"),
+                      os.path.join(OBJDIR, f"tau1_zr_{q}_{p}.o"),
                       [f"-DTAU1_Q={q}", f"-DTAU1_P={p}"]))
     cmds = [[hipcc(), *HIPCC_FLAGS, *extra, *defs, "-c", src, "-o", obj]
             for src, obj, defs in units]

@@ -73,7 +73,7 @@ tau1_status validate(const tau1_desc* d) {
     if (d->tile < -1 || d->tile >= kNumTiles) return TAU1_E_INVALID;
     if (d->layout < -1 || d->layout > 1) return TAU1_E_INVALID;
     if (d->x_boundary < 0 || d->x_boundary > 1) return TAU1_E_INVALID;
-    if (d->batch_graph < 0 || d->batch_graph > 2) return TAU1_E_INVALID;
+    if (d->batch_graph < 0 || d->batch_graph > 3) return TAU1_E_INVALID;
     for (int a = 0; a < 3; ++a)
         if (!std::isfinite(d->wall_u[a])) return TAU1_E_INVALID;
     if (d->x_boundary == 1 &&
@@ -379,6 +379,9 @@ struct tau1_ctx {
         int tile;     // its tile (the autotuner picks one per lane layout)
         bool packed;  // its samples use the packed layout
         bool chunks;  // ... and hold the chunk tile's list and records
+        int rows_mode = -1;  // >= 0: several one-row layouts in one launch
+                             // (k_zmarch_rows in this mode); variant, tile are
+                             // then those of the layout with the most work
         StepArgs args[2];
     };
     std::vector<ZGroup> zgroups;
@@ -390,6 +393,7 @@ struct tau1_ctx {
     hipGraphExec_t exec = nullptr;
     int graph_kernel = -1, graph_tile = -1, graph_parity = -1;
     bool graph_chains = false;  // batch graphs: one chain per lane layout (else one chain)
+    bool merge_rows = false;    // one launch for the one-row layouts of a batch
     double g[3] = {0, 0, 0};
     std::string cache;
     hipError_t last_hip = hipSuccess;
@@ -449,6 +453,14 @@ void* pick_d2q9(int p) {
     return nullptr;
 }
 
+// Load mode of group g's z-march kernel (a dense one-row layout in a packed
+// context runs the dense shared-row schedule), or -1 for the chunk kernel.
+int group_mode(const tau1_ctx::ZGroup& g) {
+    if (g.tile == kChunkTile && g.chunks) return -1;
+    const int zt = tile_zmarch(g.tile);
+    return tile_mode(zt) == 3 && !g.packed ? 1 : tile_mode(zt);
+}
+
 // Launch geometry of one step kernel: z-march group g (kernel 1), the
 // per-node gather over every sample (kernel 0) or the D2Q9 kernel (2).
 Launch step_launch(const tau1_ctx* ctx, int kernel, int tile, int g) {
@@ -460,12 +472,16 @@ Launch step_launch(const tau1_ctx* ctx, int kernel, int tile, int g) {
         l.block = dim3(kCkThreads);
         l.grid = dim3((unsigned)((grp.args[0].ntiles + kCkWaves - 1) / kCkWaves));
         l.shmem = 0;
+    } else if (kernel == 1 && ctx->zgroups[g].rows_mode >= 0) {
+        const auto& grp = ctx->zgroups[g];
+        l.fn = pick_zmarch_rows(ctx->lattice, ctx->precision, grp.rows_mode);
+        l.block = dim3(kZrThreads);
+        l.grid = dim3((unsigned)zmarch_grid(grp.args[0].ntiles, tile));
+        l.shmem = 0;
     } else if (kernel == 1) {
         const auto& grp = ctx->zgroups[g];
         tile = tile_zmarch(tile);
-        // a dense one-row layout in a packed context runs the dense shared-row schedule
-        const int mode = tile_mode(tile) == 3 && !grp.packed ? 1 : tile_mode(tile);
-        l.fn = pick_zmarch(ctx->lattice, ctx->precision, grp.variant, mode);
+        l.fn = pick_zmarch(ctx->lattice, ctx->precision, grp.variant, group_mode(grp));
         l.block = dim3(zmarch_threads(tile));
         l.grid = dim3((unsigned)zmarch_grid(grp.args[0].ntiles, tile));
         l.shmem = 0;
@@ -804,8 +820,12 @@ tau1_status reduce_ws(tau1_ctx* ctx, int s, int axis, double out[4]) {
 // Selects the tile of every lane layout (`tile`, or per_variant[v] where
 // that is given and not negative), rebuilds and uploads the work lists;
 // cached graphs are rebuilt on the next step.  The context's tile is that of
-// the layout with the most fluid nodes.
-tau1_status set_tile(tau1_ctx* ctx, int tile, const int* per_variant = nullptr) {
+// the layout with the most fluid nodes.  With `merge`, the one-row, one-chunk
+// layouts whose tiles run the shared-row schedule of one mode (that of the
+// layout with the most work among them) share one launch, k_zmarch_rows,
+// over their lists laid end to end; the other layouts launch alone.
+tau1_status set_tile(tau1_ctx* ctx, int tile, const int* per_variant = nullptr,
+                     bool merge = false) {
     // lane layouts present, the one with the most fluid nodes first (the
     // order of the launches of a step when they run one after another)
     std::vector<int> layouts;
@@ -818,10 +838,9 @@ tau1_status set_tile(tau1_ctx* ctx, int tile, const int* per_variant = nullptr) 
     }
     std::stable_sort(layouts.begin(), layouts.end(),
                      [&](int a, int b) { return work[a] > work[b]; });
-    std::vector<int32_t> tl;
     std::vector<tau1_ctx::ZGroup> groups;
+    std::vector<std::vector<int32_t>> parts;
     for (int v : layouts) {
-        const int64_t item0 = (int64_t)tl.size() / 4;
         tau1_ctx::ZGroup g;
         g.variant = v;
         g.tile = per_variant && per_variant[v] >= 0 ? per_variant[v] : tile;
@@ -833,32 +852,71 @@ tau1_status set_tile(tau1_ctx* ctx, int tile, const int* per_variant = nullptr) 
                 if (!sh.dev.chunk_list) g.chunks = false;
             }
         g.chunks = g.chunks && g.packed;
+        std::vector<int32_t> part;
         if (g.tile == kChunkTile && g.chunks) {
             // the chunk kernel: one item per 64 stored chunks of a sample
             for (int i = 0; i < ctx->nsamples; ++i) {
                 const auto& sh = ctx->plan.s[i];
                 if (sh.dev.variant != v) continue;
                 for (int64_t c0 = 0; c0 < sh.nch; c0 += 64) {
-                    tl.push_back(i);
-                    tl.push_back((int32_t)c0);
-                    tl.push_back((int32_t)std::min<int64_t>(64, sh.nch - c0));
-                    tl.push_back(0);
+                    part.push_back(i);
+                    part.push_back((int32_t)c0);
+                    part.push_back((int32_t)std::min<int64_t>(64, sh.nch - c0));
+                    part.push_back(0);
                 }
             }
         } else {
             const int zt = tile_zmarch(g.tile);
-            std::vector<int32_t> part =
-                zmarch_worklist(ctx->plan.s.data(), ctx->nsamples, tile_lz(zt), v,
-                                zr_share(kVariants[v].g, tile_mode(zt)));
-            tl.insert(tl.end(), part.begin(), part.end());
+            part = zmarch_worklist(ctx->plan.s.data(), ctx->nsamples, tile_lz(zt), v,
+                                   zr_share(kVariants[v].g, tile_mode(zt)));
         }
+        groups.push_back(g);
+        parts.push_back(std::move(part));
+    }
+    // the groups of the one launch, if any (at least two layouts)
+    std::vector<bool> merged(groups.size(), false);
+    int rows_mode = -1, nmerged = 0;
+    if (merge) {
+        for (size_t i = 0; i < groups.size(); ++i) {
+            const int m = group_mode(groups[i]);
+            if (!zr_rows_layout(kVariants[groups[i].variant]) || (m != 1 && m != 3)) continue;
+            if (rows_mode < 0) rows_mode = m;
+            if (m != rows_mode) continue;
+            // whole blocks of kZrWaves row items, so a block never straddles two layouts
+            if (parts[i].size() % (4 * kZrWaves) != 0) return TAU1_E_INVALID;
+            merged[i] = true;
+            ++nmerged;
+        }
+        if (nmerged < 2) merged.assign(groups.size(), false);
+    }
+    std::vector<int32_t> tl;
+    std::vector<tau1_ctx::ZGroup> launches;
+    auto add_launch = [&](tau1_ctx::ZGroup g, int64_t item0) {
         for (int p = 0; p < 2; ++p) {
             g.args[p] = ctx->args[p];
             g.args[p].tiles = reinterpret_cast<const int32_t*>(ctx->base + ctx->plan.tiles_off) +
                               4 * item0;
             g.args[p].ntiles = (int32_t)((int64_t)tl.size() / 4 - item0);
         }
-        groups.push_back(g);
+        launches.push_back(g);
+    };
+    if (nmerged >= 2) {
+        tau1_ctx::ZGroup g;
+        bool lead = true;
+        for (size_t i = 0; i < groups.size(); ++i) {
+            if (!merged[i]) continue;
+            if (lead) g = groups[i];
+            lead = false;
+            tl.insert(tl.end(), parts[i].begin(), parts[i].end());
+        }
+        g.rows_mode = rows_mode;
+        add_launch(g, 0);
+    }
+    for (size_t i = 0; i < groups.size(); ++i) {
+        if (merged[i]) continue;
+        const int64_t item0 = (int64_t)tl.size() / 4;
+        tl.insert(tl.end(), parts[i].begin(), parts[i].end());
+        add_launch(groups[i], item0);
     }
     const int64_t items = (int64_t)tl.size() / 4;
     if (items > ctx->plan.ntiles) return TAU1_E_INVALID;
@@ -868,7 +926,7 @@ tau1_status set_tile(tau1_ctx* ctx, int tile, const int* per_variant = nullptr) 
         HIP_TRY(hipStreamSynchronize(ctx->stream));
     }
     destroy_graph(ctx);
-    ctx->zgroups.swap(groups);
+    ctx->zgroups.swap(launches);
     ctx->args[0].ntiles = ctx->args[1].ntiles = (int32_t)items;
     ctx->tile = ctx->zgroups.empty() ? tile : ctx->zgroups[0].tile;
     return TAU1_OK;
@@ -983,6 +1041,7 @@ tau1_status tau1_create(const tau1_desc* desc, tau1_ctx** out) {
     ctx->ws_bytes = desc->workspace_bytes;
     ctx->cache = desc->tune_cache ? desc->tune_cache : "";
     ctx->graph_chains = desc->batch_graph != 1;
+    ctx->merge_rows = desc->batch_graph == 3;
     for (int a = 0; a < 3; ++a) ctx->g[a] = desc->g[a];
 
     const int lsr = f16_log2_scale(desc->f16_log2_scale_rho);
@@ -1067,7 +1126,7 @@ tau1_status tau1_create(const tau1_desc* desc, tau1_ctx** out) {
         if (t >= 0) tile = t;
     }
     if (zm) {
-        st = set_tile(ctx, tile);
+        st = set_tile(ctx, tile, nullptr, ctx->merge_rows);
         if (st != TAU1_OK) {
             delete ctx;
             return st;
@@ -1197,7 +1256,7 @@ tau1_status tau1_autotune(tau1_ctx* ctx, int32_t trial_steps) {
         const int t = i == 0 ? kChunkTile : i - 1;
         if (!zmarch_tile_ok(ctx->precision, ctx->plan.packed, t)) continue;
         if (t == kChunkTile && !any_chunks(ctx)) continue;
-        st = set_tile(ctx, t);
+        st = set_tile(ctx, t);  // layouts timed alone, also where they share a launch
         if (st != TAU1_OK) break;
         float total = 0.0f;
         for (int g = 0; g < (int)ctx->zgroups.size() && st == TAU1_OK; ++g) {
@@ -1230,7 +1289,7 @@ tau1_status tau1_autotune(tau1_ctx* ctx, int32_t trial_steps) {
     (void)hipEventDestroy(e1);
     if (st != TAU1_OK) return st;
     ctx->kernel = 1;
-    st = set_tile(ctx, best_tile, tile_v.data());
+    st = set_tile(ctx, best_tile, tile_v.data(), ctx->merge_rows);
     if (st != TAU1_OK) return st;
     // the cache keeps one tile per size bucket: the best single tile
     if (!ctx->cache.empty())
@@ -1258,6 +1317,10 @@ tau1_status tau1_get_info(const tau1_ctx* ctx, tau1_info* info) {
     if (ctx->kernel == 1)
         for (const auto& g : ctx->zgroups) items += g.args[0].ntiles;
     info->work_items = items;
+    int launches = 0;
+    for (int g = 0; g < launch_groups(ctx, ctx->kernel); ++g)
+        if (step_launch(ctx, ctx->kernel, ctx->tile, g).grid.x > 0) ++launches;
+    info->launches_per_step = launches;
     return TAU1_OK;
 }
 

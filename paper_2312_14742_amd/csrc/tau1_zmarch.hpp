@@ -813,7 +813,7 @@ __device__ __forceinline__ void bounce_list(const ZrItem<P, G, C, K>& it, Plane<
 // rows are read and written at their chunks' packed offsets.  Rolling
 // prefetch (mode 2, and modes 1 and 3 with G > 1): the own row of the next
 // plane (`ahead`) is requested during this plane.
-template <int Q, int P, int G, int C, int K, int NL, int MODE>
+template <int Q, int P, int G, int C, int K, int NL, int MODE, int EARLY_PX>
 __device__ __forceinline__ void zr_step(const ZrItem<P, G, C, K>& it, int zs, Planes<C * K> pl,
                                         uint32_t (&win_next)[C], uint32_t& fluid_prev,
                                         WallPipe<Q>& wp, RawRow<C * K>& ahead, PkPipe<C>& pk) {
@@ -902,10 +902,10 @@ __device__ __forceinline__ void zr_step(const ZrItem<P, G, C, K>& it, int zs, Pl
     // plane's own row has been pushed (its registers are free then; any
     // earlier and they would not fit two waves per SIMD), so its loads land
     // during the rest of the step.  Only where the workgroup's LDS already
-    // holds the CU at two waves per SIMD (six or more nodes per lane): for
-    // shorter rows the extra live registers would cost occupancy.  D3Q27's
-    // larger sums keep the request at the end of the step.
-    constexpr bool EARLY = Q < 27 && PX >= 6;
+    // holds the CU at two waves per SIMD (EARLY_PX = 6: six or more nodes per
+    // lane): for shorter rows the extra live registers would cost occupancy.
+    // D3Q27's larger sums keep the request at the end of the step.
+    constexpr bool EARLY = Q < 27 && PX >= EARLY_PX;
     if constexpr (EARLY) {
         if constexpr (PK) {
             chunk_voffs(it, tn_own, vn);
@@ -1016,7 +1016,9 @@ __device__ __forceinline__ void zero_plane(Plane<PX>& q) {
 // unrolled by three), so no partial sums are copied between planes.
 // The sample descriptor is read field by field with its own types and every
 // value is marked wave-uniform, so per-item quantities live in scalar registers.
-template <int Q, int P, int G, int C, int K, int NL, int MODE>
+// EARLY_PX: the fewest nodes per lane at which the shared-row schedules request
+// the next plane's own row right after this plane's own row is pushed.
+template <int Q, int P, int G, int C, int K, int NL, int MODE, int EARLY_PX = 6>
 __device__ __forceinline__ void zr_item(const StepArgs& a, const SampleDev* sd, int rg, int z0,
                                         int z1, float* __restrict__ lds, int wave,
                                         float* __restrict__ lds_rows) {
@@ -1115,13 +1117,13 @@ __device__ __forceinline__ void zr_item(const StepArgs& a, const SampleDev* sd, 
     }
     int zs = z0 - 1;
     while (true) {
-        zr_step<Q, P, G, C, K, NL, MODE>(it, zs, Planes<PX>{A, B, Cp}, win_next, fluid_prev, wp, rm, pk);
+        zr_step<Q, P, G, C, K, NL, MODE, EARLY_PX>(it, zs, Planes<PX>{A, B, Cp}, win_next, fluid_prev, wp, rm, pk);
         zero_plane(A);
         if (++zs > z1) break;
-        zr_step<Q, P, G, C, K, NL, MODE>(it, zs, Planes<PX>{B, Cp, A}, win_next, fluid_prev, wp, rm, pk);
+        zr_step<Q, P, G, C, K, NL, MODE, EARLY_PX>(it, zs, Planes<PX>{B, Cp, A}, win_next, fluid_prev, wp, rm, pk);
         zero_plane(B);
         if (++zs > z1) break;
-        zr_step<Q, P, G, C, K, NL, MODE>(it, zs, Planes<PX>{Cp, A, B}, win_next, fluid_prev, wp, rm, pk);
+        zr_step<Q, P, G, C, K, NL, MODE, EARLY_PX>(it, zs, Planes<PX>{Cp, A, B}, win_next, fluid_prev, wp, rm, pk);
         zero_plane(Cp);
         if (++zs > z1) break;
     }
@@ -1183,10 +1185,80 @@ void k_zmarch(StepArgs a) {
     }
 }
 
+// Nodes per lane from which k_zmarch_rows requests the next plane's own row
+// early: every layout, since every layout there runs at two waves per SIMD
+// anyway (+5 % on the 64-sample batch against the per-layout threshold).
+constexpr int kRowsEarlyPx = 1;
+
+// Lane layouts of the one-launch kernel: one row per wave in one chunk (rows
+// of 64-320 nodes).  The two-chunk rows (384, 512) would raise the kernel's
+// register demand past the two-waves-per-SIMD budget; they launch alone.
+constexpr bool zr_rows_layout(const ZrVariant& v) { return v.g == 1 && v.c == 1; }
+
+// Widest row (nodes per lane) of those layouts.
+constexpr int zr_rows_px() {
+    int m = 0;
+    for (int v = 0; v < kNumVariants; ++v)
+        if (zr_rows_layout(kVariants[v]) && kVariants[v].k > m) m = kVariants[v].k;
+    return m;
+}
+
+// Work item of lane layout v (dispatch of k_zmarch_rows): the arm of V == v
+// runs it.
+template <int Q, int P, int MODE, int V = 0>
+__device__ __forceinline__ void zr_rows_item(const StepArgs& a, int v, int s, int rg, int z0,
+                                             int z1, float* lds_all, int wave) {
+    if constexpr (V < kNumVariants) {
+        constexpr ZrVariant L = kVariants[V];
+        if constexpr (zr_rows_layout(L)) {
+            if (v == V) {
+                zr_item<Q, P, 1, 1, L.k, L.l, MODE, kRowsEarlyPx>(a, a.samples + s, rg, z0, z1,
+                                                    lds_all + wave * 4 * L.k * 64, wave, lds_all);
+                return;
+            }
+        }
+        zr_rows_item<Q, P, MODE, V + 1>(a, v, s, rg, z0, z1, lds_all, wave);
+    }
+}
+
+// Every one-row, one-chunk lane layout in one launch (rows shared through
+// LDS: mode 1 dense, mode 3 packed).  The work list is the concatenation of the layouts'
+// lists, each in blocks of kZrWaves consecutive row items (one z-segment
+// length per layout), so the four waves of a workgroup always take one block
+// of one sample and run one layout's code; the item's sample names the
+// layout.  The row slots are sized for the widest row, and the register
+// budget is that of the widest layout, so every layout runs at two waves per
+// SIMD.  The arithmetic is the per-layout kernel's, in the same order.
+template <int Q, int P, int MODE>
+__global__ __launch_bounds__(kZrThreads)
+__attribute__((amdgpu_waves_per_eu(2)))
+void k_zmarch_rows(StepArgs a) {
+    static_assert(MODE == 1 || MODE == 3, "shared-row schedules only");
+    constexpr int kLds = 2 * kZrWaves * kSlotComps * zr_rows_px() * 64;
+    __shared__ float lds_all[kLds];
+    const int wave = threadIdx.x >> 6;
+    const int nwg = gridDim.x;
+    const int b = blockIdx.x;
+    const int per = (nwg + 7) / 8;
+    const int xcd = b % 8, k = b / 8;
+    const int lb = xcd * per + k;
+    const int nwaves = ((nwg + 7) / 8) * 8 * kZrWaves;
+    const int first = __builtin_amdgcn_readfirstlane(lb * kZrWaves + wave);
+    for (int item = first; item < a.ntiles; item += nwaves) {
+        typedef int wi4 __attribute__((ext_vector_type(4)));
+        typedef const __attribute__((address_space(4))) wi4 item_t;
+        const wi4 t = ((item_t*)a.tiles)[item];
+        const int v = __builtin_amdgcn_readfirstlane(a.samples[t.x].variant);
+        zr_rows_item<Q, P, MODE>(a, v, t.x, t.y, t.z, t.w, lds_all, wave);
+    }
+}
+
 // Kernel table of one (lattice, precision) pair; defined in the per-pair
-// translation units built from tau1_zmarch_inst.hip.
+// translation units built from tau1_zmarch_inst.hip (and, for the one-launch
+// kernels of all one-row layouts, tau1_zmarch_rows.hip).
 #define TAU1_ZM_TABLE_DECL(QQ, PP) \
-    void* zm_kernel_##QQ##_##PP(int variant, int mode); void* ck_kernel_##QQ##_##PP(int k);
+    void* zm_kernel_##QQ##_##PP(int variant, int mode); void* ck_kernel_##QQ##_##PP(int k); \
+    void* zr_rows_kernel_##QQ##_##PP(int mode);
 TAU1_ZM_TABLE_DECL(15, 1) TAU1_ZM_TABLE_DECL(15, 2) TAU1_ZM_TABLE_DECL(15, 3)
 TAU1_ZM_TABLE_DECL(19, 1) TAU1_ZM_TABLE_DECL(19, 2) TAU1_ZM_TABLE_DECL(19, 3)
 TAU1_ZM_TABLE_DECL(27, 1) TAU1_ZM_TABLE_DECL(27, 2) TAU1_ZM_TABLE_DECL(27, 3)
@@ -1235,6 +1307,21 @@ inline void* pick_chunks(int q, int p, int k) {
         case 271: return ck_kernel_27_1(k);
         case 272: return ck_kernel_27_2(k);
         case 273: return ck_kernel_27_3(k);
+    }
+    return nullptr;
+}
+
+inline void* pick_zmarch_rows(int q, int p, int mode) {
+    switch (q * 10 + p) {
+        case 151: return zr_rows_kernel_15_1(mode);
+        case 152: return zr_rows_kernel_15_2(mode);
+        case 153: return zr_rows_kernel_15_3(mode);
+        case 191: return zr_rows_kernel_19_1(mode);
+        case 192: return zr_rows_kernel_19_2(mode);
+        case 193: return zr_rows_kernel_19_3(mode);
+        case 271: return zr_rows_kernel_27_1(mode);
+        case 272: return zr_rows_kernel_27_2(mode);
+        case 273: return zr_rows_kernel_27_3(mode);
     }
     return nullptr;
 }

@@ -72,7 +72,7 @@ class tau1_info(ctypes.Structure):
                 ("layout", ctypes.c_int32),
                 ("n_nodes", ctypes.c_int64), ("n_fluid", ctypes.c_int64),
                 ("steps_done", ctypes.c_int64), ("bytes_per_step", ctypes.c_double),
-                ("work_items", ctypes.c_int64)]
+                ("work_items", ctypes.c_int64), ("launches_per_step", ctypes.c_int32)]
 
 
 _LIB = None
@@ -209,6 +209,9 @@ class Sim:
     lattice (samples of shape (1, ny, nx); solid values 0 fluid, 1 wall,
     2 moving wall with velocity ``wall_u``; ``x_boundary=1`` puts Zou-He
     pressure columns at x = 0 (``rho_in``) and x = nx - 1 (``rho_out``)).
+    ``batch_graph`` shapes the launches of a batch with several lane layouts:
+    1 one chain, 2 a chain per layout side by side, 3 one launch for the
+    layouts of rows 64-320 nodes long, 0 automatic (2).
     """
 
     def __init__(self, samples, lattice=19, precision="f32", g=(0.0, 0.0, 0.0),

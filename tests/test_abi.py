@@ -81,6 +81,17 @@ def test_invalid_descriptor_rejected(lib, bad):
     assert not ctx.value
 
 
+@pytest.mark.parametrize("shape,ok", [(-1, False), (0, True), (3, True), (4, False)])
+def test_batch_graph_range(lib, shape, ok):
+    """batch_graph takes 0-3 (3: one launch for the one-chunk rows)."""
+    solid = np.zeros((4, 4, 64), np.uint8)
+    d, keep = _desc_for([(solid,), (np.zeros((4, 4, 96), np.uint8),)])
+    d.batch_graph = shape
+    n = ctypes.c_size_t(0)
+    st = lib.tau1_workspace_size(ctypes.byref(d), ctypes.byref(n))
+    assert st == (tau1.TAU1_OK if ok else tau1.TAU1_E_INVALID)
+
+
 def test_invalid_dims_rejected(lib):
     d, keep = _desc_for([(np.zeros((4, 4, 4), np.uint8),)])
     keep[0].nx = 0
