@@ -257,9 +257,11 @@ tau1_status tau1_permeability_noalloc(tau1_ctx *ctx, int32_t sample,
 
 /* Times each eligible step-kernel shape for trial_steps steps (state is not
  * advanced: trials write only the spare buffer), keeps the fastest and, if
- * the descriptor named a cache file, records it there.  Synchronous.  An
- * engineering aid of this library (the paper tunes thread counts by hand,
- * Section 4). */
+ * the descriptor named a cache file, records it there.  In a batch each lane
+ * layout is timed alone and gets its own tile; with batch_graph 3 the whole
+ * step is then timed with those tiles and with each z-march tile for every
+ * layout, and the fastest is kept.  Synchronous.  An engineering aid of this
+ * library (the paper tunes thread counts by hand, Section 4). */
 tau1_status tau1_autotune(tau1_ctx *ctx, int32_t trial_steps);
 
 /* Static facts about the context (host copy); bytes_per_step is the

@@ -1285,11 +1285,40 @@ tau1_status tau1_autotune(tau1_ctx* ctx, int32_t trial_steps) {
             best_tile = t;
         }
     }
+    // the one launch of a batch's one-chunk rows runs every layout at the
+    // occupancy of the widest, where the tiles each layout prefers alone need
+    // not be the best: its whole step is timed with those tiles and with each
+    // z-march tile for every layout, and the fastest is kept
+    int merged_tile = -1;  // -1: the per-layout tiles
+    if (st == TAU1_OK && ctx->merge_rows) {
+        ctx->kernel = 1;
+        float best_m = 1e30f;
+        for (int t = -1; t < kNumTiles && st == TAU1_OK; ++t) {
+            if (t >= 0 && (t == kChunkTile || !zmarch_tile_ok(ctx->precision, ctx->plan.packed, t)))
+                continue;
+            st = t < 0 ? set_tile(ctx, best_tile, tile_v.data(), true) : set_tile(ctx, t, nullptr, true);
+            if (st != TAU1_OK) break;
+            st = launch_one(ctx, 1, ctx->tile, ctx->parity);
+            if (st != TAU1_OK) break;
+            HIP_TRY(hipEventRecord(e0, ctx->stream));
+            for (int i = 0; i < trial_steps && st == TAU1_OK; ++i)
+                st = launch_one(ctx, 1, ctx->tile, ctx->parity);
+            HIP_TRY(hipEventRecord(e1, ctx->stream));
+            HIP_TRY(hipEventSynchronize(e1));
+            float ms = 0;
+            HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+            if (ms < best_m) {
+                best_m = ms;
+                merged_tile = t;
+            }
+        }
+    }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (st != TAU1_OK) return st;
     ctx->kernel = 1;
-    st = set_tile(ctx, best_tile, tile_v.data(), ctx->merge_rows);
+    st = merged_tile >= 0 ? set_tile(ctx, merged_tile, nullptr, true)
+                          : set_tile(ctx, best_tile, tile_v.data(), ctx->merge_rows);
     if (st != TAU1_OK) return st;
     // the cache keeps one tile per size bucket: the best single tile
     if (!ctx->cache.empty())
