@@ -813,7 +813,7 @@ __device__ __forceinline__ void bounce_list(const ZrItem<P, G, C, K>& it, Plane<
 // rows are read and written at their chunks' packed offsets.  Rolling
 // prefetch (mode 2, and modes 1 and 3 with G > 1): the own row of the next
 // plane (`ahead`) is requested during this plane.
-template <int Q, int P, int G, int C, int K, int NL, int MODE, int EARLY_PX>
+template <int Q, int P, int G, int C, int K, int NL, int MODE, bool EARLY_OK>
 __device__ __forceinline__ void zr_step(const ZrItem<P, G, C, K>& it, int zs, Planes<C * K> pl,
                                         uint32_t (&win_next)[C], uint32_t& fluid_prev,
                                         WallPipe<Q>& wp, RawRow<C * K>& ahead, PkPipe<C>& pk) {
@@ -900,12 +900,11 @@ __device__ __forceinline__ void zr_step(const ZrItem<P, G, C, K>& it, int zs, Pl
     else if constexpr (!SHARE) load_row(it, rm_, rm);
     // shared rows: the next plane's own row, requested as soon as this
     // plane's own row has been pushed (its registers are free then; any
-    // earlier and they would not fit two waves per SIMD), so its loads land
-    // during the rest of the step.  Only where the workgroup's LDS already
-    // holds the CU at two waves per SIMD (EARLY_PX = 6: six or more nodes per
-    // lane): for shorter rows the extra live registers would cost occupancy.
-    // D3Q27's larger sums keep the request at the end of the step.
-    constexpr bool EARLY = Q < 27 && PX >= EARLY_PX;
+    // earlier and they would not fit), so its loads land during the rest of
+    // the step.  Only where the instance has the registers for it at its
+    // occupancy (EARLY_OK); D3Q27's larger sums keep the request at the end
+    // of the step.
+    constexpr bool EARLY = Q < 27 && EARLY_OK;
     if constexpr (EARLY) {
         if constexpr (PK) {
             chunk_voffs(it, tn_own, vn);
@@ -1016,9 +1015,9 @@ __device__ __forceinline__ void zero_plane(Plane<PX>& q) {
 // unrolled by three), so no partial sums are copied between planes.
 // The sample descriptor is read field by field with its own types and every
 // value is marked wave-uniform, so per-item quantities live in scalar registers.
-// EARLY_PX: the fewest nodes per lane at which the shared-row schedules request
-// the next plane's own row right after this plane's own row is pushed.
-template <int Q, int P, int G, int C, int K, int NL, int MODE, int EARLY_PX = 6>
+// EARLY_OK: the shared-row schedules request the next plane's own row right
+// after this plane's own row is pushed.
+template <int Q, int P, int G, int C, int K, int NL, int MODE, bool EARLY_OK>
 __device__ __forceinline__ void zr_item(const StepArgs& a, const SampleDev* sd, int rg, int z0,
                                         int z1, float* __restrict__ lds, int wave,
                                         float* __restrict__ lds_rows) {
@@ -1117,25 +1116,49 @@ __device__ __forceinline__ void zr_item(const StepArgs& a, const SampleDev* sd, 
     }
     int zs = z0 - 1;
     while (true) {
-        zr_step<Q, P, G, C, K, NL, MODE, EARLY_PX>(it, zs, Planes<PX>{A, B, Cp}, win_next, fluid_prev, wp, rm, pk);
+        zr_step<Q, P, G, C, K, NL, MODE, EARLY_OK>(it, zs, Planes<PX>{A, B, Cp}, win_next, fluid_prev, wp, rm, pk);
         zero_plane(A);
         if (++zs > z1) break;
-        zr_step<Q, P, G, C, K, NL, MODE, EARLY_PX>(it, zs, Planes<PX>{B, Cp, A}, win_next, fluid_prev, wp, rm, pk);
+        zr_step<Q, P, G, C, K, NL, MODE, EARLY_OK>(it, zs, Planes<PX>{B, Cp, A}, win_next, fluid_prev, wp, rm, pk);
         zero_plane(B);
         if (++zs > z1) break;
-        zr_step<Q, P, G, C, K, NL, MODE, EARLY_PX>(it, zs, Planes<PX>{Cp, A, B}, win_next, fluid_prev, wp, rm, pk);
+        zr_step<Q, P, G, C, K, NL, MODE, EARLY_OK>(it, zs, Planes<PX>{Cp, A, B}, win_next, fluid_prev, wp, rm, pk);
         zero_plane(Cp);
         if (++zs > z1) break;
     }
 }
 
-// Occupancy target of an instance: the shared-row schedules (one row per
-// wave) and modes 1 and 3 on the multi-row layouts run at two waves per SIMD
-// (at most 256 registers per lane; the row slots of two workgroups fill a
-// CU's LDS); the other instances at one.  Modes 1/3 and 2 are the same
-// rolling-prefetch schedule on a multi-row layout, so the tile picks the
+// The packed shared-row schedule (mode 3) of FP32 D3Q15 and D3Q19, per lane
+// layout: the waves per SIMD its instance is built for -- the occupancy its
+// registers and row slots give without the early request of the next
+// plane's own row -- and whether it makes that request, which it does
+// wherever the extra registers fit that occupancy without spilling (not at
+// nx = 256: 4 waves and 128 registers leave no room).  +4 % on the 64-sample
+// batch against the request for six or more nodes per lane only.  The other
+// schedules, storage formats and lattices, where the same request would cost
+// occupancy or spill in some layouts, keep that rule.  (The multi-row
+// layouts have no shared-row schedule: 0 and false.)
+constexpr int kShareWaves[kNumVariants] = {5, 5, 4, 4, 3, 2, 2, 0, 5, 3, 3, 2, 0, 0, 0};
+constexpr bool kShareEarly[kNumVariants] = {true,  true, true,  false, true,  true,  true, false,
+                                            true,  true, true,  true,  false, false, false};
+
+constexpr bool zr_tabled(int q, int p, int mode) { return mode == 3 && p == kF32 && q < 27; }
+
+// Whether instance (Q, P, V, MODE) requests the next plane's own row early.
+constexpr bool zr_early(int q, int p, int v, int mode) {
+    return zr_tabled(q, p, mode) ? kShareEarly[v] : kVariants[v].c * kVariants[v].k >= 6;
+}
+
+// Occupancy target of an instance: the tabled schedules at their layout's
+// kShareWaves; the other shared-row schedules (one row per wave) and modes 1
+// and 3 on the multi-row layouts at two waves per SIMD or more (at most 256
+// registers per lane; the row slots of two workgroups fill a CU's LDS at the
+// longest rows); the other instances at one or more.  Modes 1/3 and 2 are the
+// same rolling-prefetch schedule on a multi-row layout, so the tile picks the
 // occupancy there.
-constexpr int zr_waves_per_simd(int g, int mode) {
+constexpr int zr_waves_per_simd(int q, int p, int v, int mode) {
+    const int g = kVariants[v].g;
+    if (zr_share(g, mode) && zr_tabled(q, p, mode)) return kShareWaves[v];
     return (zr_share(g, mode) || (g != 1 && (mode == 1 || mode == 3))) ? 2 : 1;
 }
 
@@ -1147,7 +1170,7 @@ constexpr int zr_waves_per_simd(int g, int mode) {
 // layout present.
 template <int Q, int P, int V, int MODE>
 __global__ __launch_bounds__(kZrThreads)
-__attribute__((amdgpu_waves_per_eu(zr_waves_per_simd(kVariants[V].g, MODE))))
+__attribute__((amdgpu_waves_per_eu(zr_waves_per_simd(Q, P, V, MODE))))
 void k_zmarch(StepArgs a) {
     static_assert(V >= 0 && V < kNumVariants, "one lane layout per instance");
     constexpr int G = kVariants[V].g, C = kVariants[V].c, K = kVariants[V].k, NL = kVariants[V].l;
@@ -1181,14 +1204,10 @@ void k_zmarch(StepArgs a) {
         typedef int wi4 __attribute__((ext_vector_type(4)));
         typedef const __attribute__((address_space(4))) wi4 item_t;
         const wi4 t = ((item_t*)a.tiles)[item];
-        zr_item<Q, P, G, C, K, NL, MODE>(a, a.samples + t.x, t.y, t.z, t.w, lds_wave, wave, lds_all);
+        zr_item<Q, P, G, C, K, NL, MODE, zr_early(Q, P, V, MODE)>(a, a.samples + t.x, t.y, t.z,
+                                                                 t.w, lds_wave, wave, lds_all);
     }
 }
-
-// Nodes per lane from which k_zmarch_rows requests the next plane's own row
-// early: every layout, since every layout there runs at two waves per SIMD
-// anyway (+5 % on the 64-sample batch against the per-layout threshold).
-constexpr int kRowsEarlyPx = 1;
 
 // Lane layouts of the one-launch kernel: one row per wave in one chunk (rows
 // of 64-320 nodes).  The two-chunk rows (384, 512) would raise the kernel's
@@ -1212,7 +1231,9 @@ __device__ __forceinline__ void zr_rows_item(const StepArgs& a, int v, int s, in
         constexpr ZrVariant L = kVariants[V];
         if constexpr (zr_rows_layout(L)) {
             if (v == V) {
-                zr_item<Q, P, 1, 1, L.k, L.l, MODE, kRowsEarlyPx>(a, a.samples + s, rg, z0, z1,
+                // every layout requests the next plane's own row early: all
+                // run at two waves per SIMD here (+5 % on the 64-sample batch)
+                zr_item<Q, P, 1, 1, L.k, L.l, MODE, true>(a, a.samples + s, rg, z0, z1,
                                                     lds_all + wave * 4 * L.k * 64, wave, lds_all);
                 return;
             }
