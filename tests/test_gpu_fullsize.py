@@ -133,3 +133,22 @@ def test_batch_of_64_samples():
             idx = sample_nodes(solid, 8000, seed=100 + i)
             # one more step for the whole batch per checked sample
             check_step(sim, i, solid, 19, "f32", g, idx, f"sample {i} side {sides[i]}")
+
+
+def test_batch_of_64_samples_one_launch():
+    """The same batch with one launch per step for every sample (batch_graph
+    3, k_zmarch_rows): sampled nodes against the oracle's update."""
+    batch = inputs.batch_recipe(64, 5000, workers=8)
+    g = (1e-3, 2e-4, -3e-4)
+    print("[case] batch of 64 samples, one launch", flush=True)
+    with tau1.Sim([tau1.Sample(b.geometry.solid) for b in batch], lattice=19, precision="f32",
+                  g=g, graph_chunk=100, batch_graph=3) as sim:
+        sim.autotune(3)
+        assert sim.info()["launches_per_step"] == 1
+        sim.step(4)
+        sides = [b.side for b in batch]
+        picks = sorted({int(np.argmin(sides)), int(np.argmax(sides)), 7, 40})
+        for i in picks:
+            solid = batch[i].geometry.solid
+            idx = sample_nodes(solid, 8000, seed=200 + i)
+            check_step(sim, i, solid, 19, "f32", g, idx, f"one launch: sample {i} side {sides[i]}")
