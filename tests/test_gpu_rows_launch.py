@@ -129,3 +129,21 @@ def test_rows_launch_autotune_bitwise():
         assert_same(tuned.moments(i), fixed.moments(i), ("autotune", i))
     fixed.close()
     tuned.close()
+
+
+def test_rows_launch_single_layout():
+    """A batch of one lane layout (and a single sample) keeps its own
+    per-layout kernel under batch_graph 3: one launch, the same bits."""
+    g = (1e-5, 0.0, 2e-6)
+    samples = [inputs.random_state(128, 6, 9, seed=9995 + i, solid_frac=0.5) for i in range(2)]
+    print("[case] rows launch, one layout", flush=True)
+    for group in (samples, samples[:1]):
+        a = make(group, 19, "f32", g, 3)
+        b = make(group, 19, "f32", g, 0)
+        assert a.info()["launches_per_step"] == 1
+        a.step(4)
+        b.step(4)
+        for i in range(len(group)):
+            assert_same(a.moments(i), b.moments(i), ("one layout", len(group), i))
+        a.close()
+        b.close()
