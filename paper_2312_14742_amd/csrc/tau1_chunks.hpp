@@ -61,14 +61,15 @@ struct CkCtx {
     float isr, isu;
 };
 
-// Lane moves across the whole wave: from lane l - 1 (ror) and from lane l + 1 (rol).
+// Lane moves across the whole wave: from lane l - 1 (ror) and from lane l + 1
+// (rol).  Every lane has a source, so no previous value is needed.
 __device__ __forceinline__ float ck_from_prev(float v) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(
-        0, __builtin_bit_cast(int, v), 0x13C, 0xf, 0xf, false));  // wave_ror:1
+    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(
+        __builtin_bit_cast(int, v), 0x13C, 0xf, 0xf, true));  // wave_ror:1
 }
 __device__ __forceinline__ float ck_from_next(float v) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(
-        0, __builtin_bit_cast(int, v), 0x134, 0xf, 0xf, false));  // wave_rol:1
+    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(
+        __builtin_bit_cast(int, v), 0x134, 0xf, 0xf, true));  // wave_rol:1
 }
 
 // Where a lane's x-neighbour chunks are: the lanes before and after it hold
@@ -241,8 +242,8 @@ void k_chunks(StepArgs a) {
     CkNb nb;
     {
         const int ei = (int)e;
-        const int ep = __builtin_amdgcn_update_dpp(0, ei, 0x13C, 0xf, 0xf, false);
-        const int en = __builtin_amdgcn_update_dpp(0, ei, 0x134, 0xf, 0xf, false);
+        const int ep = __builtin_amdgcn_mov_dpp(ei, 0x13C, 0xf, 0xf, true);
+        const int en = __builtin_amdgcn_mov_dpp(ei, 0x134, 0xf, 0xf, true);
         nb.left = lane > 0 && valid && ci > 0 && ep == ei - 1;
         nb.right = lane + 1 < t.z && ci + 1 < c.nch && en == ei + 1;
         nb.cl = ci == 0 ? c.nch - 1 : ci - 1;

@@ -113,16 +113,26 @@ inline int zr_variant_for(int nx) {
 
 // ---------------------------------------------------------------------------
 // Lane moves inside a lane group of L lanes (64 / G, or fewer for a one-row
-// layout with idle lanes).
+// layout with idle lanes).  The DPP rotations give every lane a source, so
+// they need no previous value of the destination (mov_dpp, not update_dpp).
 // up(v):   lane gl receives v from lane gl - 1 (wrapping), i.e. data moves +x
 // down(v): lane gl receives v from lane gl + 1 (wrapping), data moves -x
 // Per-lane facts the moves need: the first and last lane of the group, and
 // for L < 64 the byte addresses of the source lanes of a crossbar permute.
 // ---------------------------------------------------------------------------
 struct ZrLanes {
-    bool first, last;
+    // all ones on the group's first / last lane, else zero (bit masks for
+    // the chunk hand-over: one bitwise select instead of a compare and a
+    // conditional move)
+    uint32_t first, last;
     int up, down;
 };
+
+// Per lane: a where the mask m is all ones, b where it is zero.
+__device__ __forceinline__ float lane_pick(uint32_t m, float a, float b) {
+    const uint32_t ia = __builtin_bit_cast(uint32_t, a), ib = __builtin_bit_cast(uint32_t, b);
+    return __builtin_bit_cast(float, (ia & m) | (ib & ~m));
+}
 
 template <int G, int NL>
 __device__ __forceinline__ float lane_up(float v, const ZrLanes& ln) {
@@ -131,9 +141,9 @@ __device__ __forceinline__ float lane_up(float v, const ZrLanes& ln) {
     if constexpr (G == 1 && NL < 64) {
         r = __builtin_amdgcn_ds_bpermute(ln.up, iv);
     } else if constexpr (G == 1) {
-        r = __builtin_amdgcn_update_dpp(0, iv, 0x13C, 0xf, 0xf, false);  // wave_ror:1
+        r = __builtin_amdgcn_mov_dpp(iv, 0x13C, 0xf, 0xf, true);  // wave_ror:1
     } else if constexpr (G == 4) {
-        r = __builtin_amdgcn_update_dpp(0, iv, 0x121, 0xf, 0xf, false);  // row_ror:1
+        r = __builtin_amdgcn_mov_dpp(iv, 0x121, 0xf, 0xf, true);  // row_ror:1
     } else {
         const int lane = __lane_id();
         const int src = (lane & 32) | ((lane + 31) & 31);
@@ -149,9 +159,9 @@ __device__ __forceinline__ float lane_down(float v, const ZrLanes& ln) {
     if constexpr (G == 1 && NL < 64) {
         r = __builtin_amdgcn_ds_bpermute(ln.down, iv);
     } else if constexpr (G == 1) {
-        r = __builtin_amdgcn_update_dpp(0, iv, 0x134, 0xf, 0xf, false);  // wave_rol:1
+        r = __builtin_amdgcn_mov_dpp(iv, 0x134, 0xf, 0xf, true);  // wave_rol:1
     } else if constexpr (G == 4) {
-        r = __builtin_amdgcn_update_dpp(0, iv, 0x12F, 0xf, 0xf, false);  // row_ror:15
+        r = __builtin_amdgcn_mov_dpp(iv, 0x12F, 0xf, 0xf, true);  // row_ror:15
     } else {
         const int lane = __lane_id();
         const int src = (lane & 32) | ((lane + 1) & 31);
@@ -367,8 +377,8 @@ __device__ __forceinline__ void push_dir(Planes<C * K>& pl, const Src (&s)[C * K
         for (int c = 0; c < C; ++c) {
             float v = edge[c];
             if constexpr (C > 1) {
-                if constexpr (CX > 0) v = ln.first ? edge[(c + C - 1) % C] : v;
-                else v = ln.last ? edge[(c + 1) % C] : v;
+                if constexpr (CX > 0) v = lane_pick(ln.first, edge[(c + C - 1) % C], v);
+                else v = lane_pick(ln.last, edge[(c + 1) % C], v);
             }
             add_to<CX, CY, CZ, C * K>(pl, CX > 0 ? c * K : c * K + K - 1, w, v);
         }
@@ -1034,8 +1044,8 @@ __device__ __forceinline__ void zr_item(const StepArgs& a, const SampleDev* sd, 
     // offsets are out of range (no loads, no stores) and the lane moves skip
     // them (each keeps its own value)
     const bool idle = it.gl >= NL;
-    it.ln.first = it.gl == 0;
-    it.ln.last = it.gl == NL - 1;
+    it.ln.first = it.gl == 0 ? ~0u : 0u;
+    it.ln.last = it.gl == NL - 1 ? ~0u : 0u;
     it.ln.up = (idle ? it.gl : (it.gl == 0 ? NL - 1 : it.gl - 1)) << 2;
     it.ln.down = (idle ? it.gl : (it.gl == NL - 1 ? 0 : it.gl + 1)) << 2;
     it.nx = __builtin_amdgcn_readfirstlane(sd->nx);
